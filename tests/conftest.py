@@ -1,0 +1,27 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+@pytest.fixture(scope="session")
+def grids():
+    from synth import make_grid
+
+    cache = {}
+
+    def get(n, k):
+        if (n, k) not in cache:
+            cache[(n, k)] = make_grid(n, k)
+        return cache[(n, k)]
+
+    return get

@@ -1,0 +1,186 @@
+"""Pins of the oracle's time step against invariants and physics (CPU).
+
+Each pin targets a part of the step where a plausible slip would show:
+  * resting isothermal atmosphere stays bitwise at rest (whole step);
+  * total mass conserved to round-off (flux form, column increments);
+  * horizontally uniform fields produce no horizontal tendencies (bitwise);
+  * a balanced zonal jet stays steady, and does not with the Coriolis sign
+    flipped (Coriolis, kinetic-energy gradient, pressure gradient signs);
+  * a column balanced by the input generator's own discrete hydrostatic
+    integration keeps w ~ 0, an unbalanced one does not (implicit solver,
+    buoyancy and vertical pressure-gradient signs);
+  * vertical advection signs, diffusion and divergence damping dissipate,
+    Smagorinsky sees no deformation in rigid rotation, the least-squares
+    vertex vector is exact for a uniform tangent vector.
+"""
+import numpy as np
+import pytest
+
+from oracle import dycore
+from oracle import operators as op
+from oracle.constants import default_params
+from oracle.grid import Grid
+from synth import build_workload, initial_state, make_grid
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    g0, S, vert, spec = build_workload("r2b2_k30")
+    return Grid(g0, vert), S, spec
+
+
+@pytest.fixture(scope="module")
+def r2b3():
+    return make_grid(2, 3)
+
+
+def test_rest_state_bitwise(cfg1):
+    g, _, spec = cfg1
+    g0, S, vert, _ = build_workload("r2b2_k30_rest")
+    S1 = S
+    for _ in range(10):
+        S1 = dycore.step(g, S1, spec["dt"], spec["nsub"])
+    for k in S:
+        assert np.array_equal(S1[k], S[k]), k
+
+
+def test_mass_conservation(cfg1):
+    g, S, spec = cfg1
+    m0 = dycore.diag(g, S)["mass"]
+    S1 = S
+    for _ in range(10):
+        S1 = dycore.step(g, S1, spec["dt"], spec["nsub"])
+    d = dycore.diag(g, S1)
+    assert abs(d["mass"] / m0 - 1.0) <= 1e-13
+    assert d["n_nonfinite"] == 0
+    assert d["max_abs_vn"] < 10.0 and d["max_abs_w"] < 1.0  # stays bounded
+
+
+def test_horizontally_uniform_symmetry(r2b3):
+    S, vert = initial_state(r2b3, 12, 20e3, seed=0)
+    g = Grid(r2b3, vert)
+    S["theta_v"] = S["theta_v"] + np.linspace(0.0, 3.0, 12)[:, None]  # unbalanced, uniform
+    S1 = dycore.step(g, S, 300.0, 3)
+    assert np.all(S1["vn"] == 0.0)
+    for k in ("w", "rho", "exner", "theta_v"):
+        assert np.all(S1[k] == S1[k][:, :1]), k
+    assert np.abs(S1["w"]).max() > 1e-3  # the column did evolve
+
+
+def test_balanced_jet_steady_and_coriolis_sign(r2b3):
+    S, vert = initial_state(r2b3, 20, 30e3, seed=0, jet_u0=35.0)
+    g = Grid(r2b3, vert)
+    p = default_params()
+    S1 = dycore.step(g, S, 300.0, 5, p)
+    assert np.abs(S1["vn"] - S["vn"]).max() < 0.05
+    p2 = dict(p)
+    p2["omega"] = -p["omega"]
+    S2 = dycore.step(g, S, 300.0, 5, p2)
+    assert np.abs(S2["vn"] - S["vn"]).max() > 0.5
+
+
+def test_balanced_warm_column_keeps_w_zero(r2b3):
+    prof = 4.0 * np.sin(np.linspace(0.0, np.pi, 16))
+    S, vert = initial_state(r2b3, 16, 20e3, seed=0, t_profile=prof)
+    g = Grid(r2b3, vert)
+    S1 = dycore.step(g, S, 300.0, 5)
+    assert np.abs(S1["w"]).max() < 1e-9
+    # the same temperatures with the reference Exner (not balanced) must move
+    Sb = dict(S)
+    Sb["exner"] = np.repeat(g.ex_ref[:, None], g.nc, axis=1)
+    Sb["rho"] = 1.0e5 * Sb["exner"] ** (717.6 / 287.04) / (287.04 * Sb["theta_v"])
+    S2 = dycore.step(g, Sb, 300.0, 5)
+    assert np.abs(S2["w"]).max() > 1e-3
+
+
+def test_vertical_advection_signs(r2b3):
+    S, vert = initial_state(r2b3, 10, 10e3, seed=0)
+    g = Grid(r2b3, vert)
+    p = default_params()
+    K = 10
+    # vn increasing with height (k = 0 is the top), w > 0 in the interior
+    vn = np.repeat(np.linspace(10.0, 1.0, K)[:, None], g.ne, axis=1)
+    w = np.zeros((K + 1, g.nc))
+    w[1:K] = 0.5
+    t_vn, _ = dycore.velocity_advection(g, p, vn, w)
+    t_vn0, _ = dycore.velocity_advection(g, p, vn, np.zeros_like(w))
+    vert_part = (t_vn - t_vn0)[1:K - 1]
+    assert np.all(vert_part < 0.0)  # upward motion brings slower air from below
+    w2 = np.zeros((K + 1, g.nc))
+    w2[1:K] = np.linspace(1.0, 0.1, K - 1)[:, None]  # w decreasing downward, upward motion
+    _, t_w = dycore.velocity_advection(g, p, np.zeros((K, g.ne)), w2)
+    # -w dw/dz with dw/dz > 0 and w > 0 -> negative
+    assert np.all(t_w[2:K - 1] < 0.0)
+    assert np.all(t_w[0] == 0.0) and np.all(t_w[K] == 0.0)
+
+
+def test_diffusion_and_divergence_damping_dissipate(r2b3):
+    S, vert = initial_state(r2b3, 6, 10e3, seed=4, vn_sigma=2.0, jet_u0=20.0)
+    g = Grid(r2b3, vert)
+    p = default_params()
+    e0 = np.sum(g.a_e * S["vn"] ** 2)
+    S1 = dycore.diffusion(g, p, S, 600.0)
+    assert np.sum(g.a_e * S1["vn"] ** 2) < e0
+    # the corrector's damping increment alone reduces the divergence
+    inc = -p["divdamp_c4"] * g.mean_area**2 * dycore.divergence_damping(g, S["vn"])
+    d0 = np.sum(g.a_c * op.div(g, S["vn"]) ** 2)
+    d1 = np.sum(g.a_c * op.div(g, S["vn"] + inc) ** 2)
+    assert d1 < d0
+
+
+def test_smagorinsky_rigid_rotation_vs_shear(r2b3):
+    _, vert = initial_state(r2b3, 1, 10e3, seed=0)
+    g = Grid(r2b3, vert)
+    p = default_params()
+    w = dycore.vertex_lsq_weights(g)
+    om = 1e-5
+    u = om * g.radius * np.cross(np.array([0.0, 0.0, 1.0]), g.xe)
+    vn = np.einsum("ej,ej->e", u, g.nrm)[None]
+    vv = np.einsum("vjs,kvs->kvj", w, np.where(g.v2e[None] >= 0, vn[:, np.maximum(g.v2e, 0)], 0.0))
+    nu_rot = dycore.smagorinsky_nu(g, p, vv, 1.0)
+    # zonal shear flow u = U z (z = sin lat), deformation ~ U / R
+    u2 = 10.0 * g.xe[:, 2:3] * np.cross(np.array([0.0, 0.0, 1.0]), g.xe)
+    vn2 = np.einsum("ej,ej->e", u2, g.nrm)[None]
+    vv2 = np.einsum("vjs,kvs->kvj", w, np.where(g.v2e[None] >= 0, vn2[:, np.maximum(g.v2e, 0)], 0.0))
+    nu_sh = dycore.smagorinsky_nu(g, p, vv2, 1.0)
+    def_rot = np.median(nu_rot / (p["smag_cs"] * g.a_e)) / om
+    def_sh = np.median(nu_sh / (p["smag_cs"] * g.a_e)) / (10.0 / g.radius)
+    assert def_rot < 0.05
+    assert 0.3 < def_sh < 3.0
+
+
+def test_lsq_vertex_vector_exact_for_tangent_vector(r2b3):
+    _, vert = initial_state(r2b3, 1, 10e3, seed=0)
+    g = Grid(r2b3, vert)
+    w = dycore.vertex_lsq_weights(g)
+    rng = np.random.default_rng(0)
+    U = rng.normal(size=(g.nv, 3))
+    U -= np.einsum("vj,vj->v", U, g.xv)[:, None] * g.xv  # tangent at each vertex
+    ok = g.v2e >= 0
+    vn_v = np.where(ok, np.einsum("vsj,vj->vs", g.nrm[np.maximum(g.v2e, 0)], U), 0.0)
+    rec = np.einsum("vjs,vs->vj", w, vn_v)
+    assert np.abs(rec - U).max() < 1e-12 * np.abs(U).max()
+
+
+def test_smagorinsky_cap(r2b3):
+    S, vert = initial_state(r2b3, 3, 10e3, seed=9, vn_sigma=50.0)
+    g = Grid(r2b3, vert)
+    p = default_params()
+    w = dycore.vertex_lsq_weights(g)
+    vv = np.einsum("vjs,kvs->kvj", w, np.where(g.v2e[None] >= 0, S["vn"][:, np.maximum(g.v2e, 0)], 0.0))
+    dt = 1.0e5
+    nu = dycore.smagorinsky_nu(g, p, vv, dt)
+    assert np.all(nu >= 0.0)
+    assert np.all(nu <= g.a_e / (p["smag_cap"] * dt))
+    assert np.any(nu == g.a_e / (p["smag_cap"] * dt))
+
+
+def test_equation_of_state_round_trip():
+    g = make_grid(2, 1)
+    S, vert = initial_state(g, 8, 20e3, seed=3, jet_u0=35.0, n_bumps=4, bump_radius=2000e3)
+    ex = (287.04 * S["rho"] * S["theta_v"] / 1.0e5) ** (287.04 / 717.6)
+    assert np.max(np.abs(ex / S["exner"] - 1)) < 1e-14
+    # jet surface pressure: equator/pole ratio of the gradient-wind balance
+    from synth.state import _surface_pressure_jet
+    r = _surface_pressure_jet(np.array([0.0]), 35.0, 6.371e6)[0] / _surface_pressure_jet(np.array([np.pi / 2]), 35.0, 6.371e6)[0]
+    assert abs(r - 1.168) < 1e-3

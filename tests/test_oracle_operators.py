@@ -1,0 +1,134 @@
+"""Pins of the oracle's C-grid operators against mathematics (CPU).
+
+Each test is chosen so that a plausible slip in an operator (wrong sign,
+transposed index, wrong length or area) fails: discrete identities that hold
+to round-off (constant gradient, summation by parts, curl-grad, div-gradt),
+and convergence to closed forms of solid-body rotation on the sphere.
+"""
+import numpy as np
+import pytest
+
+from oracle import operators as op
+from oracle.grid import Grid
+from synth import make_grid, vertical, reference
+
+
+def _grid(n, k, K=3):
+    zh, zf = vertical(K, 10e3)
+    return Grid(make_grid(n, k), {"z_half": zh, **reference(zh, zf)})
+
+
+@pytest.fixture(scope="module")
+def g2():
+    return _grid(2, 2)
+
+
+def _solid_body(g, omega=1e-5):
+    """Normal wind of rigid rotation about z: u = omega z_hat x r."""
+    u = omega * g.radius * np.cross(np.array([0.0, 0.0, 1.0]), g.xe)
+    return np.einsum("ej,ej->e", u, g.nrm)[None, :], u
+
+
+def test_grad_constant_is_zero(g2):
+    p = np.full((3, g2.nc), 987.654321)
+    assert np.all(op.grad(g2, p) == 0.0)
+
+
+def test_summation_by_parts(g2):
+    rng = np.random.default_rng(0)
+    phi = rng.normal(size=(3, g2.nc))
+    F = rng.normal(size=(3, g2.ne))
+    lhs = np.sum(g2.a_c * phi * op.div(g2, F), axis=1)
+    rhs = np.sum(g2.l_e * g2.d_e * F * op.grad(g2, phi), axis=1)
+    scale = np.sum(np.abs(g2.l_e * g2.d_e * F * op.grad(g2, phi)), axis=1)
+    assert np.all(np.abs(lhs + rhs) / scale < 1e-13)
+
+
+def test_curl_grad_and_div_gradt_vanish(g2):
+    rng = np.random.default_rng(1)
+    phi = rng.normal(size=(2, g2.nc))
+    psi = rng.normal(size=(2, g2.nv))
+    gp = op.grad(g2, phi)
+    c = op.curl(g2, gp) * g2.a_v
+    ref = np.abs(g2.d_e * gp).max()
+    assert np.abs(c).max() < 1e-13 * ref
+    gt = op.gradt(g2, psi)
+    d = op.div(g2, gt) * g2.a_c
+    assert np.abs(d).max() < 1e-13 * np.abs(g2.l_e * gt).max()
+
+
+def test_solid_body_curl_converges():
+    errs = []
+    omega = 1e-5
+    for k in (2, 3, 4, 5):
+        g = _grid(2, k, K=1)
+        vn, _ = _solid_body(g, omega)
+        z = op.curl(g, vn)[0]
+        errs.append(np.max(np.abs(z - 2 * omega * g.xv[:, 2])) / (2 * omega))
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 2e-3
+
+
+def test_solid_body_divergence_converges_and_lapv_bounded():
+    """Div of a rigid rotation converges to 0 (first order); the plain triangular
+    vector Laplacian is only zeroth-order accurate, so only a bound is pinned."""
+    omega = 1e-5
+    dmax = []
+    for k in (2, 3, 4, 5):
+        g = _grid(2, k, K=1)
+        vn, _ = _solid_body(g, omega)
+        dmax.append(np.max(np.abs(op.div(g, vn)[0])) / omega)
+        L = op.lapv(g, vn)[0]
+        want = -2.0 / g.radius**2 * vn[0]
+        rms = np.sqrt(np.mean((L - want) ** 2) / np.mean(want**2))
+        assert rms < 0.06
+    assert all(b < 0.6 * a for a, b in zip(dmax, dmax[1:]))
+
+
+def test_lapv_adjoint_identity(g2):
+    """<F, lapv G>_e = -<div F, div G>_c - <curl F, curl G>_v (both summations by parts)."""
+    rng = np.random.default_rng(5)
+    F = rng.normal(size=(2, g2.ne))
+    G = rng.normal(size=(2, g2.ne))
+    lhs = np.sum(g2.l_e * g2.d_e * F * op.lapv(g2, G), axis=1)
+    rhs = -(np.sum(g2.a_c * op.div(g2, F) * op.div(g2, G), axis=1)
+            + np.sum(g2.a_v * op.curl(g2, F) * op.curl(g2, G), axis=1))
+    assert np.all(np.abs(lhs - rhs) < 1e-12 * np.abs(rhs).max())
+
+
+def test_perot_tangential_converges():
+    omega = 1e-5
+    errs = []
+    for k in (2, 3, 4, 5):
+        g = _grid(2, k, K=1)
+        vn, u = _solid_body(g, omega)
+        vt = op.recon_vt(g, vn)[0]
+        want = np.einsum("ej,ej->e", u, g.tan)
+        errs.append(np.max(np.abs(vt - want)) / (omega * g.radius))
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 5e-3
+
+
+def test_scalar_laplacian_is_div_grad(g2):
+    """laps must equal div(grad): the same telescoping, written the other way round."""
+    rng = np.random.default_rng(2)
+    phi = rng.normal(size=(2, g2.nc))
+    a = op.laps(g2, phi)
+    b = op.div(g2, op.grad(g2, phi))
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
+
+
+def test_level_averages():
+    q = np.arange(12.0).reshape(4, 3)
+    h = op.ih(q)
+    assert h.shape == (5, 3)
+    assert np.all(h[0] == q[0]) and np.all(h[-1] == q[-1])
+    assert np.all(h[2] == 0.5 * (q[1] + q[2]))
+    assert np.all(op.fh(h)[1] == 0.5 * (h[1] + h[2]))
+
+
+def test_cell_and_edge_means(g2):
+    c = np.full((1, g2.nc), 3.0)
+    e = np.full((1, g2.ne), 5.0)
+    assert np.all(op.avg_e(g2, c) == 3.0)
+    assert np.all(op.avg_c(g2, e) == 5.0)
