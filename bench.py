@@ -1,0 +1,201 @@
+"""Throughput of the dycore time step on one MI355X (plus the oracle on the host).
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload r2b5_k65]
+
+A step is one dc_dycore_step: nsub predictor-corrector substeps and one
+diffusion step over the whole grid.  Inputs are resident in HBM when the
+timed region starts.  Prints one JSON line (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dycore cell·level·steps/s, % HBM peak; mixed/surrogate vs FP64 at stated err"
+HBM_PEAK_GBS = 8000.0
+FIELDS = ("vn", "w", "rho", "exner", "theta_v")
+
+
+def kernel_bytes(C, E, V, K, r):
+    """Algorithmic bytes of one launch of each kernel: every array the kernel
+    reads or writes counted once per (entity, level); r = bytes of vn and of
+    the horizontal intermediates (8 FP64, 4 mixed); cell prognostics are 8."""
+    KE, KV, KC, K1C = K * E, K * V, K * C, (K + 1) * C
+    return {
+        "curl_pred": r * (KE + KV),
+        "vt_pred": r * 2 * KE,
+        "cell_adv_pred": r * 2 * KE + 8 * K1C + r * (KC + K1C),
+        "edge_pred": r * 2 * KE + r * KV + r * KC + 8 * K1C + 8 * 2 * KC + r * 2 * KE,
+        "column_pred": r * KE + 8 * K1C + r * K1C + 8 * 3 * KC + 8 * K1C,
+        "curl_corr": r * (KE + KV),
+        "vt_corr": r * 2 * KE,
+        "cell_adv_corr": r * 2 * KE + 8 * K1C + r * (KC + K1C + KC),
+        "edge_corr": r * 4 * KE + r * KV + r * 2 * KC + 8 * K1C + 8 * 2 * KC + r * KE,
+        "column_corr": r * KE + 8 * K1C + r * 2 * K1C + 8 * 3 * KC + 8 * (K1C + 3 * KC),
+        "diff_vertex": r * KE + r * 4 * KV,
+        "diff_div": r * KE + r * KC,
+        "diff_edge1": r * KC + r * 4 * KV + r * 2 * KE,
+        "diff_cell_vertex2": r * 2 * KE + 8 * 2 * K1C + r * (KC + KV),
+        "diff_edge2": r * 3 * KE + r * KC + r * KV + r * KE,
+    }
+
+
+def step_algorithmic_bytes(C, E, K, nsub, r):
+    """Compulsory HBM traffic of a whole step with perfect fusion: each
+    substep reads the state once for the predictor and once (plus the
+    predicted vn, w) for the corrector and writes the new state; diffusion
+    reads and writes vn and w once."""
+    state = r * K * E + 8 * ((K + 1) * C + 3 * K * C)
+    pred = state + r * K * E + 8 * (K + 1) * C            # read S^n, write vn*, w*
+    corr = state + r * K * E + 8 * (K + 1) * C + state    # read S^n, vn*, w*, write S^{n+1}
+    diff = 2 * (r * K * E + 8 * (K + 1) * C)
+    return nsub * (pred + corr) + diff
+
+
+def cpu_baseline(spec, g0, S, vert, budget_s=25.0):
+    """The oracle, as it stands, on one host core for a bounded sample."""
+    import numpy as np
+
+    from oracle import dycore as O
+    from oracle.constants import default_params
+    from oracle.grid import Grid as OGrid
+
+    try:
+        old = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(old)})
+    except (AttributeError, OSError):
+        old = None
+    try:
+        og = OGrid(g0, vert)
+        wts = O.vertex_lsq_weights(og)
+        p = default_params()
+        t0 = time.perf_counter()
+        steps = 0
+        Sx = S
+        while True:
+            Sx = O.step(og, Sx, spec["dt"], spec["nsub"], p, wts=wts)
+            steps += 1
+            if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 3:
+                break
+        el = time.perf_counter() - t0
+    finally:
+        if old is not None:
+            os.sched_setaffinity(0, old)
+    units = og.nc * og.n_lev * steps
+    return {"value": units / el, "unit": "cell·level·steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full step(s) of the same workload ({og.nc} cells x {og.n_lev} levels, nsub "
+                      f"{spec['nsub']}), NumPy FP64 oracle pinned to one core, {el:.1f} s; host os.cpu_count()="
+                      f"{os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="r2b5_k65")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--sfc", type=int, default=-1, help="1/0 force the Morton renumbering; -1 workload default")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2608_21150_amd import dycore as D
+    from synth import WORKLOADS, build_workload
+
+    spec = WORKLOADS[args.workload]
+    sfc = bool(spec.get("sfc", 0)) if args.sfc < 0 else bool(args.sfc)
+    print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
+    g0, S, vert, spec = build_workload(args.workload)
+    C, E, V, K = g0["n_cells"], g0["n_edges"], g0["n_verts"], spec["n_lev"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    G = D.Grid(g0, vert, sfc=sfc)
+
+    def run(precision, steps, warmup, profile):
+        st = D.State(G, precision=precision, device=dev)
+        st.write(S)
+        for _ in range(warmup):
+            st.step(spec["dt"], spec["nsub"])
+        torch.cuda.synchronize()
+        if profile:
+            st.profile(True)
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            st.step(spec["dt"], spec["nsub"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        prof = st.profile_read() if profile else None
+        out = st.read()
+        d = st.diag()
+        st.close()
+        return ms, prof, out, d
+
+    print(f"[bench] {args.precision}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+    ms, prof, out, diag = run(args.precision, args.steps, args.warmup, True)
+    ms_step = ms / args.steps
+    value = C * K * args.steps / (ms / 1e3)
+    r = 4 if args.precision == "mixed" else 8
+    kb = kernel_bytes(C, E, V, K, r)
+    kernels = {}
+    for name, (calls, tot) in prof.items():
+        if calls:
+            avg = tot / calls
+            kernels[name] = {"calls": calls, "avg_us": avg * 1e3, "GBps": kb[name] / (avg * 1e-3) / 1e9,
+                             "share": tot / sum(t for _, t in prof.values())}
+    dom = max(kernels, key=lambda n: kernels[n]["share"])
+    dk = kernels[dom]
+    achieved = dk["GBps"]
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": kb[dom], "avg_launch_us": round(dk["avg_us"], 2)}
+    b_step = step_algorithmic_bytes(C, E, K, spec["nsub"], r)
+    line = {
+        "metric": METRIC, "value": value, "unit": "cell·level·steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: R{g0['n']}B{g0['k']} icosahedral grid, {C} cells, {E} edges, "
+                               f"{V} vertices, {K} levels, dt {spec['dt']} s, {spec['nsub']} substeps, "
+                               f"{'Morton-ordered' if sfc else 'generator-ordered'}, {args.precision}",
+                   "cells": C, "levels": K, "dt": spec["dt"], "nsub": spec["nsub"], "precision": args.precision},
+        "roofline": roof,
+        "step_hbm_effective_frac": round(b_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_algorithmic_bytes_per_cell_level": b_step / (C * K),
+        "kernels": {n: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+                    for n, d in kernels.items()},
+        "diag": {"mass": diag["mass"], "n_nonfinite": diag["n_nonfinite"]},
+    }
+    if args.precision == "fp64" and not args.no_mixed:
+        print("[bench] mixed precision run", file=sys.stderr, flush=True)
+        ms2, _, out2, d2 = run("mixed", args.steps, args.warmup, False)
+        errs = {k: float(np.linalg.norm(out2[k] - out[k]) / np.linalg.norm(out[k])) for k in FIELDS}
+        line["mixed"] = {"value": C * K * args.steps / (ms2 / 1e3), "ms_per_step": ms2 / args.steps,
+                         "speedup_vs_fp64": ms / ms2, "rel_l2_vs_fp64": errs,
+                         "after_steps": args.steps + args.warmup,
+                         "mass_rel_diff_vs_fp64": d2["mass"] / diag["mass"] - 1.0}
+    G.close()
+    if not args.no_cpu_baseline:
+        print("[bench] oracle on the host", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(spec, g0, S, vert)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * dycore.h -- C ABI of the MI355X (gfx950) ICON-style non-hydrostatic
+ * dynamical-core time step.
+ *
+ * The operation: one time step of length dt = nsub dynamic substeps of length
+ * dt/nsub (each a predictor and a corrector that start with the advective
+ * tendencies, update the horizontal momentum with pressure gradient and
+ * advection, damp divergence in the corrector only and advance w, rho, Exner
+ * and theta_v with a vertically implicit column solver), followed by one
+ * diffusion step (Smagorinsky plus fourth-order background on vn, second
+ * order on w).  Paper: Section 4.1 and the caption of Fig. 1 (time-step
+ * structure), Section 5.1 "Experimental setup" (substep / diffusion split,
+ * RnBk icosahedral grids), Section 4.3.1 (C-ABI conventions: scalars by value,
+ * arrays by reference without copies, double-buffered prognostic arrays, an
+ * interface independent of the implementation).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns a dc_status.  A call that fails validation returns
+ *    its error without enqueuing work or changing any state; the message is
+ *    available from dc_last_error() (thread-local).
+ *  - Device errors of asynchronous work surface at the next synchronising
+ *    call (dc_state_read/write, dc_diag_conservation, destroy) as DC_EHIP.
+ *  - Host arrays are plain C arrays, row-major.  Device field buffers are
+ *    [level][entity] with the entity index fastest and each level padded to
+ *    the stride reported by dc_grid_info_get (a multiple of 64 entities).
+ *  - One host thread per state at a time; different states are independent.
+ *  - GPU: the library uses the current HIP device at dc_grid_create.
+ */
+#ifndef DYCORE_H
+#define DYCORE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dc_grid dc_grid;
+typedef struct dc_state dc_state;
+typedef struct dc_ensemble dc_ensemble;
+
+typedef enum {
+  DC_OK = 0,
+  DC_EINVAL = -1,      /* NULL pointer, bad size, bad enum, misaligned buffer   */
+  DC_EGRID = -2,       /* inconsistent connectivity or geometry                 */
+  DC_EHIP = -3,        /* a HIP runtime call or kernel failed                   */
+  DC_ENOMEM = -4,      /* device or host allocation failed                      */
+  DC_ENONFINITE = -5,  /* check_finite set and the state holds NaN/Inf          */
+  DC_EBUSY = -6,       /* grid destroyed while states still use it              */
+  DC_ESTATE = -7       /* operation not valid in the state's configuration      */
+} dc_status;
+
+typedef enum { DC_PREC_FP64 = 0, DC_PREC_MIXED = 1 } dc_precision;
+/* DC_DIFF_NONE skips the diffusion step (used to measure what diffusion adds). */
+typedef enum { DC_DIFF_PLAIN = 0, DC_DIFF_SURROGATE = 1, DC_DIFF_NONE = 2 } dc_diffusion;
+
+/*
+ * Grid description (all host pointers; dc_grid_create copies everything).
+ * Horizontal: the RnBk triangular grid of the paper's Section 5.1.
+ *   e2c   [E][2] the two cells of an edge; the normal points e2c[e][0] -> e2c[e][1]
+ *   c2e   [C][3] the three edges of a cell (any order; canonicalised)
+ *   e2v   [E][2] the two vertices of an edge (any order; ordered along the tangent)
+ *   c2e2c [C][3] the three neighbour cells (any order; validated as a set)
+ *   vert_xyz, cell_xyz, edge_xyz [.][3] unit position vectors (cell = circumcentre,
+ *                                  edge = normalised vertex midpoint)
+ *   edge_length l_e, dual_edge_length d_e [E] metres; cell_area [C], dual_area [V] m^2
+ *   edge_normal_xyz [E][3] unit normal, tangent to the sphere at edge_xyz
+ * Vertical: height-based column, level 0 at the model top.
+ *   z_half [K+1] strictly decreasing; exner_ref_full, theta_ref_full [K];
+ *   theta_ref_half, dexner_dz_ref_half [K+1]: the reference atmosphere
+ *   (pi0, theta0 at full levels, theta0 and d pi0/dz at half levels).
+ * sfc_reorder = 1 renumbers cells, edges and vertices along a Morton curve of
+ * the circumcentres (locality of neighbour gathers).  Host arrays passed to
+ * dc_state_read/write always use the caller's original numbering.
+ */
+typedef struct {
+  int32_t n_cells, n_edges, n_verts, n_lev;
+  const int32_t *e2c, *c2e, *e2v, *c2e2c;
+  const double *vert_xyz, *cell_xyz, *edge_xyz;
+  const double *edge_length, *dual_edge_length;
+  const double *cell_area, *dual_area;
+  const double *edge_normal_xyz;
+  const double *z_half;
+  const double *exner_ref_full, *theta_ref_full;
+  const double *theta_ref_half, *dexner_dz_ref_half;
+  double radius;
+  int32_t sfc_reorder;
+} dc_grid_desc;
+
+typedef struct {
+  int32_t n_cells, n_edges, n_verts, n_lev;
+  int32_t cell_stride, edge_stride, vert_stride; /* padded level strides, entities */
+} dc_grid_info;
+
+/* Table ids for dc_grid_table (internal numbering; int32, row-major). */
+enum {
+  DC_TAB_E2C = 0,   /* [E][2]                                                     */
+  DC_TAB_C2E,       /* [C][3] counter-clockwise; c2e[c][i] joins c2v[i], c2v[i+1] */
+  DC_TAB_E2V,       /* [E][2] ordered along the tangent t = r x n                 */
+  DC_TAB_C2E2C,     /* [C][3] cell across c2e[c][i]                               */
+  DC_TAB_C2V,       /* [C][3] counter-clockwise seen from outside                 */
+  DC_TAB_V2E,       /* [V][6] counter-clockwise from the smallest id, -1 padded   */
+  DC_TAB_V2C,       /* [V][6] cell between v2e[i] and v2e[i+1], -1 padded         */
+  DC_TAB_E2C2E,     /* [E][4] other edges of c0, then of c1, in c2e order         */
+  DC_TAB_E2C2V,     /* [E][4] v0, v1, vertex of c0 off e, vertex of c1 off e      */
+  DC_TAB_PERM_CELL, /* [C] original id of internal cell i (identity without SFC)  */
+  DC_TAB_PERM_EDGE, /* [E]                                                        */
+  DC_TAB_PERM_VERT, /* [V]                                                        */
+  DC_TAB_COUNT
+};
+
+/*
+ * Scheme parameters.  Defaults (dc_params_default) are the documented
+ * readings of the paper's unstated constants.
+ */
+typedef struct {
+  double eta;            /* implicit weight of the column solver (0.65)                 */
+  double adv_w0, adv_w1; /* corrector weights of the two advective tendencies (.25/.75)  */
+  double divdamp_c4;     /* 4th-order divergence damping: c4 * mean_cell_area^2 (0.0025)  */
+  double rayleigh_tau0;  /* sponge rate [1/s] (0.05)                                      */
+  double rayleigh_zfrac; /* sponge starts at this fraction of the model top (2/3)         */
+  double smag_cs;        /* Smagorinsky constant (0.015)                                  */
+  double smag_cap;       /* nu <= A_e / (smag_cap * dt) (16)                              */
+  double hdiff_k4;       /* background 4th-order diffusion k4 * A_e^2 (1/128)             */
+  double rd, cpd, cvd;   /* gas constant, heat capacities of dry air                      */
+  double omega;          /* planetary angular velocity [1/s]                              */
+  int32_t diffuse_w;     /* 1: diffuse w with the Smagorinsky viscosity                   */
+  int32_t check_finite;  /* 1: dc_dycore_step checks the state and returns DC_ENONFINITE  */
+} dc_params;
+
+/* Device pointers of the five prognostic fields, [level][entity] padded.
+ * FP64 mode: all double.  Mixed mode: vn float, the others double.
+ * vn [K][edge_stride], w [K+1][cell_stride], rho/exner/theta_v [K][cell_stride].
+ * Every pointer must be 256-byte aligned. */
+typedef struct { void *vn, *w, *rho, *exner, *theta_v; } dc_fields;
+
+enum { DC_FIELD_VN = 0, DC_FIELD_W, DC_FIELD_RHO, DC_FIELD_EXNER, DC_FIELD_THETA_V, DC_FIELD_COUNT };
+
+typedef struct {
+  double mass;        /* sum_c A_c sum_j rho dz_j                 [kg]  */
+  double theta_mass;  /* sum_c A_c sum_j rho theta_v dz_j         [kg K] */
+  double max_abs_w, max_abs_vn;
+  int64_t n_nonfinite; /* NaN/Inf entries over the five fields           */
+} dc_diag;
+
+/* Validate the description, derive canonical tables, orientation and
+ * stencil coefficients on the host, upload them to the current device.
+ * DC_EGRID when: an index is out of range; e2c/c2e/e2v/c2e2c disagree; an
+ * edge is not in exactly two cells; V - E + C != 2; a length or area <= 0;
+ * n_e . (x_c1 - x_c0) <= 0; a vertex has more than 6 edges.  Memory owned by
+ * the grid is released by dc_grid_destroy. */
+dc_status dc_grid_create(const dc_grid_desc *desc, dc_grid **out);
+dc_status dc_grid_info_get(const dc_grid *grid, dc_grid_info *info);
+/* Copy a derived table (see DC_TAB_*) to host_out, which holds n int32. */
+dc_status dc_grid_table(const dc_grid *grid, int32_t table_id, int32_t *host_out, size_t n);
+/* DC_EBUSY while states created on the grid are alive. */
+dc_status dc_grid_destroy(dc_grid *grid);
+
+dc_status dc_params_default(dc_params *p);
+
+/* Bytes of one device field buffer (padded) in the given precision. */
+dc_status dc_field_bytes(const dc_grid *grid, dc_precision prec, int32_t field, size_t *bytes);
+/* Bytes of the caller-provided device workspace a state needs. */
+dc_status dc_state_workspace_bytes(const dc_grid *grid, dc_precision prec, dc_diffusion diff, size_t *bytes);
+
+/* Create a state over caller-owned device buffers (borrowed, never freed
+ * by the library; keep them alive until dc_state_destroy).  bufA holds the
+ * initial state; each substep writes the other buffer set and flips.
+ * stream: a hipStream_t (NULL = the null stream); all work is enqueued
+ * there asynchronously. */
+dc_status dc_state_create(const dc_grid *grid, const dc_params *params, dc_precision prec,
+                          dc_diffusion diff, dc_fields bufA, dc_fields bufB, void *workspace,
+                          size_t workspace_bytes, void *stream, dc_state **out);
+/* 0: bufA holds the latest state, 1: bufB. */
+dc_status dc_state_current(const dc_state *st, int32_t *which);
+/* Synchronising host copies of one field in FP64, unpadded [level][entity],
+ * original numbering; n must equal the field's element count. */
+dc_status dc_state_read(dc_state *st, int32_t field, double *host, size_t n);
+dc_status dc_state_write(dc_state *st, int32_t field, const double *host, size_t n);
+/* One time step: nsubsteps predictor-corrector substeps of dt/nsubsteps,
+ * then diffusion with dt.  Asynchronous on the state's stream.
+ * DC_EINVAL: dt <= 0 or not finite, nsubsteps < 1. */
+dc_status dc_dycore_step(dc_state *st, double dt, int32_t nsubsteps);
+/* Synchronising conservation diagnostics of the current buffer (fixed
+ * reduction order: reproducible run to run). */
+dc_status dc_diag_conservation(dc_state *st, dc_diag *out);
+dc_status dc_state_destroy(dc_state *st);
+
+/* Per-kernel timing with HIP events recorded on the state's stream around
+ * every launch of dc_dycore_step (paper, Section 4.3.3: the profile of one
+ * substep, launch versus execution).  enable != 0 clears and starts the
+ * record, 0 stops it.  dc_state_profile_read synchronises and fills one
+ * entry per kernel kind (cap >= 15): name, launches, summed duration. */
+typedef struct {
+  char name[32];
+  int64_t calls;
+  double total_ms;
+} dc_kernel_stat;
+dc_status dc_state_profile(dc_state *st, int32_t enable);
+dc_status dc_state_profile_read(dc_state *st, dc_kernel_stat *out, int32_t cap, int32_t *n_out);
+
+/* Batched ensemble: members (any grids, same precision) stepped together by
+ * one hipGraph launch whose kernels each cover every member through a
+ * per-launch work table.  Members keep their own buffers and stream-less
+ * semantics: the graph is launched on the first member's stream. */
+dc_status dc_ensemble_create(dc_state *const *members, int32_t n_members, dc_ensemble **out);
+dc_status dc_ensemble_step(dc_ensemble *ens, double dt, int32_t nsubsteps);
+dc_status dc_ensemble_destroy(dc_ensemble *ens);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *dc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DYCORE_H */

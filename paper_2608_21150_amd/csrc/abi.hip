@@ -1,0 +1,621 @@
+// C-ABI entry points of the dycore library: grid and state lifecycle, the
+// time step (dynamic substeps, then diffusion), host copies and diagnostics.
+// The call conventions follow the paper's Fortran/C bridge (Section 4.3.1):
+// scalars by value, arrays by reference without copies, double-buffered
+// prognostic fields flipped by the library, and nothing of the kernel
+// implementation visible in the interface.
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace dc {
+
+thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace dc
+
+using namespace dc;
+
+struct dc_grid {
+  HostGrid h;
+  DevGrid d{};
+  bool uploaded = false;
+  int device = -1;
+  std::vector<void*> allocs;
+  std::atomic<int> states{0};
+};
+
+struct dc_state {
+  dc_grid* grid = nullptr;
+  dc_params p{};
+  dc_precision prec = DC_PREC_FP64;
+  dc_diffusion diff = DC_DIFF_PLAIN;
+  dc_fields buf[2]{};
+  int cur = 0;
+  hipStream_t stream = nullptr;
+  DevGrid d{};  // grid view plus per-state Coriolis and sponge tables
+  Tile tiles[T_COUNT];
+  Prof prof;
+  // workspace carve-up
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  void *vt, *tvn0, *vns, *kc, *tw0, *tw1, *d2, *zeta, *vv;
+  double *wstar, *cp, *dp, *drx, *dxx, *wtmp, *fe, *tau, *diag_part, *diag_out;
+};
+
+namespace {
+
+#define DC_TRY(expr)                                                                  \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(_e));                   \
+      return DC_EHIP;                                                                 \
+    }                                                                                 \
+  } while (0)
+
+dc_status fail(dc_status code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+size_t elem_size(dc_precision prec) { return prec == DC_PREC_MIXED ? sizeof(float) : sizeof(double); }
+
+struct Layout {
+  size_t vt, tvn0, vns, kc, tw0, tw1, d2, zeta, vv, wstar, cp, dp, drx, dxx, wtmp, fe, tau, dpart, dout, total;
+};
+
+Layout workspace_layout(const HostGrid& h, dc_precision prec) {
+  const size_t r = elem_size(prec);
+  const size_t K = h.K, K1 = h.K + 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  Layout L;
+  L.vt = take(K * h.es * r);
+  L.tvn0 = take(K * h.es * r);
+  L.vns = take(K * h.es * r);
+  L.kc = take(K * h.cs * r);
+  L.tw0 = take(K1 * h.cs * r);
+  L.tw1 = take(K1 * h.cs * r);
+  L.d2 = take(K1 * h.cs * r);
+  L.zeta = take(K * h.vs * r);
+  L.vv = take(3 * K * h.vs * r);
+  L.wstar = take(K1 * h.cs * 8);
+  L.cp = take(K1 * h.cs * 8);
+  L.dp = take(K1 * h.cs * 8);
+  L.drx = take(K1 * h.cs * 8);
+  L.dxx = take(K1 * h.cs * 8);
+  L.wtmp = take(K1 * h.cs * 8);
+  L.fe = take(h.es * 8);
+  L.tau = take(K1 * 8);
+  const int nblk = (h.nc + 255) / 256 + (h.ne + 255) / 256;
+  L.dpart = take(5 * (size_t)nblk * 8);
+  L.dout = take(8 * 8);
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+dc_status upload(dc_grid* g, const std::vector<T>& v, const T** out) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 256);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(DC_ENOMEM, std::string("hipMalloc(grid table): ") + hipGetErrorString(e));
+  g->allocs.push_back(p);
+  if (!v.empty()) DC_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<const T*>(p);
+  return DC_OK;
+}
+
+dc_status ensure_uploaded(dc_grid* g) {
+  if (g->uploaded) return DC_OK;
+  const HostGrid& h = g->h;
+  DevGrid& d = g->d;
+  d.nc = h.nc;
+  d.ne = h.ne;
+  d.nv = h.nv;
+  d.K = h.K;
+  d.cs = h.cs;
+  d.es = h.es;
+  d.vs = h.vs;
+  dc_status st;
+#define UP(vec, field) \
+  if ((st = upload(g, vec, &d.field)) != DC_OK) return st;
+  UP(h.t_c2e, c2e);
+  UP(h.t_c2e2c, c2e2c);
+  UP(h.k_div, kdiv);
+  UP(h.k_lap, klap);
+  UP(h.k_area, area);
+  UP(h.t_e2c, e2c);
+  UP(h.t_e2v, e2v);
+  UP(h.t_e2c2e, e2c2e);
+  UP(h.t_e2c2v, e2c2v);
+  UP(h.k_vt, kvt);
+  UP(h.k_invd, invd);
+  UP(h.k_invl, invl);
+  UP(h.k_ae, ae);
+  UP(h.k_invlr, invlr);
+  UP(h.k_nrm, nrm);
+  UP(h.k_tan, tan);
+  UP(h.t_v2e, v2e);
+  UP(h.k_curl, kcurl);
+  UP(h.k_lsq, klsq);
+  UP(h.vert, vert);
+#undef UP
+  d.fe = nullptr;
+  d.tau = nullptr;
+  DC_TRY(hipGetDevice(&g->device));
+  g->uploaded = true;
+  return DC_OK;
+}
+
+bool aligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) % 256 == 0); }
+
+size_t field_elems(const HostGrid& h, int field) {
+  switch (field) {
+    case DC_FIELD_VN: return (size_t)h.K * h.es;
+    case DC_FIELD_W: return (size_t)(h.K + 1) * h.cs;
+    default: return (size_t)h.K * h.cs;
+  }
+}
+size_t field_host_elems(const HostGrid& h, int field) {
+  switch (field) {
+    case DC_FIELD_VN: return (size_t)h.K * h.ne;
+    case DC_FIELD_W: return (size_t)(h.K + 1) * h.nc;
+    default: return (size_t)h.K * h.nc;
+  }
+}
+void* field_ptr(const dc_fields& f, int field) {
+  switch (field) {
+    case DC_FIELD_VN: return f.vn;
+    case DC_FIELD_W: return f.w;
+    case DC_FIELD_RHO: return f.rho;
+    case DC_FIELD_EXNER: return f.exner;
+    default: return f.theta_v;
+  }
+}
+
+void default_tiles(const HostGrid& h, Tile* t) {
+  // levels per block so that each launch has a few thousand blocks when the
+  // grid is large, and one level per block on small grids
+  auto kb_for = [&](int n, int levels) {
+    const int nbx = (n + 255) / 256;
+    int kb = (int)((long long)levels * nbx / 2048);
+    return std::max(1, std::min(kb, 16));
+  };
+  t[T_CURL] = {256, kb_for(h.nv, h.K)};
+  t[T_VT] = {256, kb_for(h.ne, h.K)};
+  t[T_CELLADV] = {256, kb_for(h.nc, h.K + 1)};
+  t[T_EDGE] = {256, kb_for(h.ne, h.K)};
+  t[T_COL] = {64, 1};
+  t[T_DVERT] = {256, kb_for(h.nv, h.K)};
+  t[T_DCELL] = {256, kb_for(h.nc + h.nv, h.K + 1)};
+  t[T_DEDGE] = {256, kb_for(h.ne, h.K)};
+}
+
+StepCoef make_coef(const dc_state* s, double dt, int nsub) {
+  StepCoef c{};
+  c.dtau = dt / nsub;
+  c.dt = dt;
+  c.eta = s->p.eta;
+  c.a0 = s->p.adv_w0;
+  c.a1 = s->p.adv_w1;
+  c.cpd = s->p.cpd;
+  c.rd_cvd = s->p.rd / s->p.cvd;
+  c.cvd_rd = s->p.cvd / s->p.rd;
+  c.c4a2 = s->p.divdamp_c4 * s->grid->h.mean_area * s->grid->h.mean_area;
+  c.cs = s->p.smag_cs;
+  c.cap = s->p.smag_cap;
+  c.k4 = s->p.hdiff_k4;
+  c.diffuse_w = s->p.diffuse_w;
+  return c;
+}
+
+template <typename R>
+void enqueue_step(dc_state* s, double dt, int nsub) {
+  const StepCoef c = make_coef(s, dt, nsub);
+  const bool diffuse = s->diff != DC_DIFF_NONE;
+  for (int i = 0; i < nsub; ++i) {
+    const dc_fields& cur = s->buf[s->cur];
+    const dc_fields& nxt = s->buf[1 - s->cur];
+    const bool last = i == nsub - 1;
+    Bufs<R> b{};
+    b.vn = static_cast<const R*>(cur.vn);
+    b.w = static_cast<const double*>(cur.w);
+    b.rho = static_cast<const double*>(cur.rho);
+    b.ex = static_cast<const double*>(cur.exner);
+    b.th = static_cast<const double*>(cur.theta_v);
+    b.vt = static_cast<R*>(s->vt);
+    b.tvn0 = static_cast<R*>(s->tvn0);
+    b.vns = static_cast<R*>(s->vns);
+    b.kc = static_cast<R*>(s->kc);
+    b.tw0 = static_cast<R*>(s->tw0);
+    b.tw1 = static_cast<R*>(s->tw1);
+    b.d2 = static_cast<R*>(s->d2);
+    b.zeta = static_cast<R*>(s->zeta);
+    b.vv = static_cast<R*>(s->vv);
+    b.ws = s->wstar;
+    b.cp = s->cp;
+    b.dp = s->dp;
+    b.drx = s->drx;
+    b.dxx = s->dxx;
+    b.wtmp = s->wtmp;
+    b.vn_out = static_cast<R*>(nxt.vn);
+    b.w_out = (last && diffuse) ? s->wtmp : static_cast<double*>(nxt.w);
+    b.rho_out = static_cast<double*>(nxt.rho);
+    b.ex_out = static_cast<double*>(nxt.exner);
+    b.th_out = static_cast<double*>(nxt.theta_v);
+    launch_substep<R>(s->d, b, c, s->tiles, s->stream, &s->prof);
+    s->cur ^= 1;
+  }
+  if (diffuse) {
+    const dc_fields& cur = s->buf[s->cur];
+    launch_diffusion<R>(s->d, static_cast<R*>(cur.vn), s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt),
+                        static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
+                        static_cast<R*>(s->zeta), static_cast<R*>(s->vv), c, s->tiles, s->stream, &s->prof);
+  }
+}
+
+dc_status run_diag(dc_state* s, dc_diag* out) {
+  const dc_fields& f = s->buf[s->cur];
+  if (s->prec == DC_PREC_MIXED)
+    launch_diag<float>(s->d, static_cast<const float*>(f.vn), static_cast<const double*>(f.w),
+                       static_cast<const double*>(f.rho), static_cast<const double*>(f.theta_v),
+                       static_cast<const double*>(f.exner), s->diag_part, s->diag_out, s->stream);
+  else
+    launch_diag<double>(s->d, static_cast<const double*>(f.vn), static_cast<const double*>(f.w),
+                        static_cast<const double*>(f.rho), static_cast<const double*>(f.theta_v),
+                        static_cast<const double*>(f.exner), s->diag_part, s->diag_out, s->stream);
+  DC_TRY(hipGetLastError());
+  double h[5];
+  DC_TRY(hipMemcpyAsync(h, s->diag_out, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  DC_TRY(hipStreamSynchronize(s->stream));
+  out->mass = h[0];
+  out->theta_mass = h[1];
+  out->max_abs_w = h[2];
+  out->max_abs_vn = h[3];
+  out->n_nonfinite = (int64_t)h[4];
+  return DC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dc_last_error(void) { return g_last_error.c_str(); }
+
+dc_status dc_params_default(dc_params* p) {
+  if (!p) return fail(DC_EINVAL, "params is NULL");
+  p->eta = 0.65;
+  p->adv_w0 = 0.25;
+  p->adv_w1 = 0.75;
+  p->divdamp_c4 = 0.0025;
+  p->rayleigh_tau0 = 0.05;
+  p->rayleigh_zfrac = 2.0 / 3.0;
+  p->smag_cs = 0.015;
+  p->smag_cap = 16.0;
+  p->hdiff_k4 = 1.0 / 128.0;
+  p->rd = 287.04;
+  p->cpd = 1004.64;
+  p->cvd = 1004.64 - 287.04;
+  p->omega = 7.29212e-5;
+  p->diffuse_w = 1;
+  p->check_finite = 0;
+  return DC_OK;
+}
+
+dc_status dc_grid_create(const dc_grid_desc* desc, dc_grid** out) {
+  if (!out) return fail(DC_EINVAL, "out is NULL");
+  *out = nullptr;
+  dc_grid* g = new (std::nothrow) dc_grid();
+  if (!g) return fail(DC_ENOMEM, "host allocation failed");
+  std::string err;
+  int rc;
+  try {
+    rc = build_host_grid(desc, &g->h, &err);
+  } catch (const std::bad_alloc&) {
+    rc = DC_ENOMEM;
+    err = "host allocation failed";
+  }
+  if (rc != DC_OK) {
+    delete g;
+    return fail((dc_status)rc, err);
+  }
+  *out = g;
+  set_error("");
+  return DC_OK;
+}
+
+dc_status dc_grid_info_get(const dc_grid* g, dc_grid_info* info) {
+  if (!g || !info) return fail(DC_EINVAL, "NULL argument");
+  info->n_cells = g->h.nc;
+  info->n_edges = g->h.ne;
+  info->n_verts = g->h.nv;
+  info->n_lev = g->h.K;
+  info->cell_stride = g->h.cs;
+  info->edge_stride = g->h.es;
+  info->vert_stride = g->h.vs;
+  return DC_OK;
+}
+
+dc_status dc_grid_table(const dc_grid* g, int32_t id, int32_t* out, size_t n) {
+  if (!g || !out) return fail(DC_EINVAL, "NULL argument");
+  const HostGrid& h = g->h;
+  const std::vector<int32_t>* t = nullptr;
+  switch (id) {
+    case DC_TAB_E2C: t = &h.e2c; break;
+    case DC_TAB_C2E: t = &h.c2e; break;
+    case DC_TAB_E2V: t = &h.e2v; break;
+    case DC_TAB_C2E2C: t = &h.c2e2c; break;
+    case DC_TAB_C2V: t = &h.c2v; break;
+    case DC_TAB_V2E: t = &h.v2e; break;
+    case DC_TAB_V2C: t = &h.v2c; break;
+    case DC_TAB_E2C2E: t = &h.e2c2e; break;
+    case DC_TAB_E2C2V: t = &h.e2c2v; break;
+    case DC_TAB_PERM_CELL: t = &h.perm_c; break;
+    case DC_TAB_PERM_EDGE: t = &h.perm_e; break;
+    case DC_TAB_PERM_VERT: t = &h.perm_v; break;
+    default: return fail(DC_EINVAL, "unknown table id");
+  }
+  if (n != t->size()) return fail(DC_EINVAL, "table size mismatch: expected " + std::to_string(t->size()));
+  std::memcpy(out, t->data(), n * sizeof(int32_t));
+  return DC_OK;
+}
+
+dc_status dc_grid_destroy(dc_grid* g) {
+  if (!g) return fail(DC_EINVAL, "grid is NULL");
+  if (g->states.load() > 0) return fail(DC_EBUSY, "grid still has live states");
+  for (void* p : g->allocs) (void)hipFree(p);
+  delete g;
+  return DC_OK;
+}
+
+dc_status dc_field_bytes(const dc_grid* g, dc_precision prec, int32_t field, size_t* bytes) {
+  if (!g || !bytes) return fail(DC_EINVAL, "NULL argument");
+  if (prec != DC_PREC_FP64 && prec != DC_PREC_MIXED) return fail(DC_EINVAL, "bad precision");
+  if (field < 0 || field >= DC_FIELD_COUNT) return fail(DC_EINVAL, "bad field id");
+  const size_t es = (field == DC_FIELD_VN && prec == DC_PREC_MIXED) ? 4 : 8;
+  *bytes = field_elems(g->h, field) * es;
+  return DC_OK;
+}
+
+dc_status dc_state_workspace_bytes(const dc_grid* g, dc_precision prec, dc_diffusion diff, size_t* bytes) {
+  if (!g || !bytes) return fail(DC_EINVAL, "NULL argument");
+  if (prec != DC_PREC_FP64 && prec != DC_PREC_MIXED) return fail(DC_EINVAL, "bad precision");
+  if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE) return fail(DC_EINVAL, "unsupported diffusion mode");
+  *bytes = workspace_layout(g->h, prec).total;
+  return DC_OK;
+}
+
+dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precision prec, dc_diffusion diff,
+                          dc_fields a, dc_fields b, void* workspace, size_t ws_bytes, void* stream, dc_state** out) {
+  if (!gc || !params || !out) return fail(DC_EINVAL, "NULL argument");
+  *out = nullptr;
+  dc_grid* g = const_cast<dc_grid*>(gc);
+  if (prec != DC_PREC_FP64 && prec != DC_PREC_MIXED) return fail(DC_EINVAL, "bad precision");
+  if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE) return fail(DC_EINVAL, "unsupported diffusion mode");
+  const dc_fields* bs[2] = {&a, &b};
+  for (int i = 0; i < 2; ++i)
+    for (int f = 0; f < DC_FIELD_COUNT; ++f)
+      if (!aligned(field_ptr(*bs[i], f))) return fail(DC_EINVAL, "field buffers must be non-NULL and 256-byte aligned");
+  const Layout L = workspace_layout(g->h, prec);
+  if (!aligned(workspace)) return fail(DC_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  if (ws_bytes < L.total) return fail(DC_EINVAL, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  const dc_params& p = *params;
+  if (!(p.eta >= 0.5 && p.eta <= 1.0) || !(p.rd > 0 && p.cpd > p.rd && p.cvd > 0) || !(p.smag_cap > 0) ||
+      !(p.rayleigh_zfrac > 0 && p.rayleigh_zfrac < 1) || p.rayleigh_tau0 < 0 || p.divdamp_c4 < 0 || p.hdiff_k4 < 0 ||
+      p.smag_cs < 0 || !std::isfinite(p.omega))
+    return fail(DC_EINVAL, "parameter out of range");
+  dc_status st = ensure_uploaded(g);
+  if (st != DC_OK) return st;
+  int dev = -1;
+  DC_TRY(hipGetDevice(&dev));
+  if (dev != g->device) return fail(DC_EINVAL, "state must be created on the grid's device");
+
+  dc_state* s = new (std::nothrow) dc_state();
+  if (!s) return fail(DC_ENOMEM, "host allocation failed");
+  s->grid = g;
+  s->p = p;
+  s->prec = prec;
+  s->diff = diff;
+  s->buf[0] = a;
+  s->buf[1] = b;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->ws = static_cast<char*>(workspace);
+  s->ws_bytes = ws_bytes;
+  char* w = s->ws;
+  s->vt = w + L.vt;
+  s->tvn0 = w + L.tvn0;
+  s->vns = w + L.vns;
+  s->kc = w + L.kc;
+  s->tw0 = w + L.tw0;
+  s->tw1 = w + L.tw1;
+  s->d2 = w + L.d2;
+  s->zeta = w + L.zeta;
+  s->vv = w + L.vv;
+  s->wstar = reinterpret_cast<double*>(w + L.wstar);
+  s->cp = reinterpret_cast<double*>(w + L.cp);
+  s->dp = reinterpret_cast<double*>(w + L.dp);
+  s->drx = reinterpret_cast<double*>(w + L.drx);
+  s->dxx = reinterpret_cast<double*>(w + L.dxx);
+  s->wtmp = reinterpret_cast<double*>(w + L.wtmp);
+  s->fe = reinterpret_cast<double*>(w + L.fe);
+  s->tau = reinterpret_cast<double*>(w + L.tau);
+  s->diag_part = reinterpret_cast<double*>(w + L.dpart);
+  s->diag_out = reinterpret_cast<double*>(w + L.dout);
+  // per-state tables: Coriolis parameter and sponge profile
+  const HostGrid& h = g->h;
+  std::vector<double> fe(h.es, 0.0), tau(h.K + 1, 0.0);
+  for (int e = 0; e < h.ne; ++e) fe[e] = 2.0 * p.omega * h.xe[3 * e + 2];
+  const double ztop = h.z_half[0], zd = p.rayleigh_zfrac * ztop;
+  for (int k = 0; k <= h.K; ++k) {
+    const double z = h.z_half[k];
+    if (z > zd) {
+      const double sn = std::sin(0.5 * M_PI * (z - zd) / (ztop - zd));
+      tau[k] = p.rayleigh_tau0 * sn * sn;
+    }
+  }
+  hipError_t e1 = hipMemcpy(s->fe, fe.data(), fe.size() * 8, hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(s->tau, tau.data(), tau.size() * 8, hipMemcpyHostToDevice);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    delete s;
+    return fail(DC_EHIP, std::string("hipMemcpy(state tables): ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  s->d = g->d;
+  s->d.fe = s->fe;
+  s->d.tau = s->tau;
+  default_tiles(h, s->tiles);
+  g->states.fetch_add(1);
+  *out = s;
+  return DC_OK;
+}
+
+dc_status dc_state_current(const dc_state* s, int32_t* which) {
+  if (!s || !which) return fail(DC_EINVAL, "NULL argument");
+  *which = s->cur;
+  return DC_OK;
+}
+
+dc_status dc_state_read(dc_state* s, int32_t field, double* host, size_t n) {
+  if (!s || !host) return fail(DC_EINVAL, "NULL argument");
+  if (field < 0 || field >= DC_FIELD_COUNT) return fail(DC_EINVAL, "bad field id");
+  const HostGrid& h = s->grid->h;
+  if (n != field_host_elems(h, field)) return fail(DC_EINVAL, "host array size mismatch");
+  const size_t ne_pad = field_elems(h, field);
+  const bool f32 = field == DC_FIELD_VN && s->prec == DC_PREC_MIXED;
+  std::vector<double> tmp(ne_pad);
+  std::vector<float> tmpf(f32 ? ne_pad : 0);
+  DC_TRY(hipStreamSynchronize(s->stream));
+  void* src = field_ptr(s->buf[s->cur], field);
+  if (f32)
+    DC_TRY(hipMemcpy(tmpf.data(), src, ne_pad * 4, hipMemcpyDeviceToHost));
+  else
+    DC_TRY(hipMemcpy(tmp.data(), src, ne_pad * 8, hipMemcpyDeviceToHost));
+  const int stride = field == DC_FIELD_VN ? h.es : h.cs;
+  const int nent = field == DC_FIELD_VN ? h.ne : h.nc;
+  const std::vector<int32_t>& perm = field == DC_FIELD_VN ? h.perm_e : h.perm_c;
+  const int levels = field == DC_FIELD_W ? h.K + 1 : h.K;
+  for (int k = 0; k < levels; ++k)
+    for (int i = 0; i < nent; ++i) {
+      const size_t src_i = (size_t)k * stride + i;
+      host[(size_t)k * nent + perm[i]] = f32 ? (double)tmpf[src_i] : tmp[src_i];
+    }
+  return DC_OK;
+}
+
+dc_status dc_state_write(dc_state* s, int32_t field, const double* host, size_t n) {
+  if (!s || !host) return fail(DC_EINVAL, "NULL argument");
+  if (field < 0 || field >= DC_FIELD_COUNT) return fail(DC_EINVAL, "bad field id");
+  const HostGrid& h = s->grid->h;
+  if (n != field_host_elems(h, field)) return fail(DC_EINVAL, "host array size mismatch");
+  const size_t ne_pad = field_elems(h, field);
+  const bool f32 = field == DC_FIELD_VN && s->prec == DC_PREC_MIXED;
+  const int stride = field == DC_FIELD_VN ? h.es : h.cs;
+  const int nent = field == DC_FIELD_VN ? h.ne : h.nc;
+  const std::vector<int32_t>& perm = field == DC_FIELD_VN ? h.perm_e : h.perm_c;
+  const int levels = field == DC_FIELD_W ? h.K + 1 : h.K;
+  std::vector<double> tmp(f32 ? 0 : ne_pad, 0.0);
+  std::vector<float> tmpf(f32 ? ne_pad : 0, 0.0f);
+  for (int k = 0; k < levels; ++k)
+    for (int i = 0; i < nent; ++i) {
+      const double x = host[(size_t)k * nent + perm[i]];
+      const size_t dst = (size_t)k * stride + i;
+      if (f32)
+        tmpf[dst] = (float)x;
+      else
+        tmp[dst] = x;
+    }
+  DC_TRY(hipStreamSynchronize(s->stream));
+  void* dstp = field_ptr(s->buf[s->cur], field);
+  if (f32)
+    DC_TRY(hipMemcpy(dstp, tmpf.data(), ne_pad * 4, hipMemcpyHostToDevice));
+  else
+    DC_TRY(hipMemcpy(dstp, tmp.data(), ne_pad * 8, hipMemcpyHostToDevice));
+  return DC_OK;
+}
+
+dc_status dc_dycore_step(dc_state* s, double dt, int32_t nsub) {
+  if (!s) return fail(DC_EINVAL, "state is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DC_EINVAL, "dt must be finite and > 0");
+  if (nsub < 1 || nsub > 1000) return fail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
+  if (s->prec == DC_PREC_MIXED)
+    enqueue_step<float>(s, dt, nsub);
+  else
+    enqueue_step<double>(s, dt, nsub);
+  DC_TRY(hipGetLastError());
+  if (s->p.check_finite) {
+    dc_diag d;
+    dc_status st = run_diag(s, &d);
+    if (st != DC_OK) return st;
+    if (d.n_nonfinite > 0) return fail(DC_ENONFINITE, "state holds non-finite values");
+  }
+  return DC_OK;
+}
+
+dc_status dc_diag_conservation(dc_state* s, dc_diag* out) {
+  if (!s || !out) return fail(DC_EINVAL, "NULL argument");
+  return run_diag(s, out);
+}
+
+dc_status dc_state_profile(dc_state* s, int32_t enable) {
+  if (!s) return fail(DC_EINVAL, "state is NULL");
+  DC_TRY(hipStreamSynchronize(s->stream));
+  s->prof.on = enable != 0;
+  s->prof.used = 0;
+  return DC_OK;
+}
+
+dc_status dc_state_profile_read(dc_state* s, dc_kernel_stat* out, int32_t cap, int32_t* n_out) {
+  if (!s || !out || !n_out || cap < K_COUNT) return fail(DC_EINVAL, "NULL argument or capacity < kernel count");
+  DC_TRY(hipStreamSynchronize(s->stream));
+  for (int k = 0; k < K_COUNT; ++k) {
+    std::memset(out[k].name, 0, sizeof(out[k].name));
+    std::strncpy(out[k].name, kKernelNames[k], sizeof(out[k].name) - 1);
+    out[k].calls = 0;
+    out[k].total_ms = 0.0;
+  }
+  const Prof& p = s->prof;
+  for (size_t i = 0; i + 1 < p.used; ++i) {
+    if (p.kid[i] >= 0 && p.kid[i + 1] == -1) {
+      float ms = 0.f;
+      DC_TRY(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+      out[p.kid[i]].calls += 1;
+      out[p.kid[i]].total_ms += ms;
+    }
+  }
+  *n_out = K_COUNT;
+  return DC_OK;
+}
+
+dc_status dc_state_destroy(dc_state* s) {
+  if (!s) return fail(DC_EINVAL, "state is NULL");
+  hipError_t e = hipStreamSynchronize(s->stream);
+  for (hipEvent_t ev : s->prof.ev) (void)hipEventDestroy(ev);
+  s->grid->states.fetch_sub(1);
+  delete s;
+  if (e != hipSuccess) return fail(DC_EHIP, std::string("pending work failed: ") + hipGetErrorString(e));
+  return DC_OK;
+}
+
+dc_status dc_ensemble_create(dc_state* const*, int32_t, dc_ensemble** out) {
+  if (out) *out = nullptr;
+  return fail(DC_ESTATE, "ensemble stepping is not available in this build");
+}
+dc_status dc_ensemble_step(dc_ensemble*, double, int32_t) { return fail(DC_ESTATE, "ensemble stepping is not available in this build"); }
+dc_status dc_ensemble_destroy(dc_ensemble*) { return fail(DC_ESTATE, "ensemble stepping is not available in this build"); }
+
+}  // extern "C"

@@ -1,0 +1,470 @@
+// Host grid layer: validation, optional Morton renumbering, canonical
+// connectivity, orientation signs and stencil coefficients.
+//
+// Neighbour access on the icosahedral grid goes through index lookup tables
+// (paper, Section 4.2.1); the grid is the RnBk construction of Section 5.1.
+// Canonical orders (they are readings; the paper fixes none):
+//   e2v[e]     ordered so that (x_v1 - x_v0) . t_e > 0, t_e = x_e x n_e
+//   c2e[c]     input order if it runs counter-clockwise seen from outside,
+//              else slots 1 and 2 swapped; c2e[c][i] joins c2v[i], c2v[i+1]
+//   c2v[c][i]  common vertex of c2e[c][i-1] and c2e[c][i]
+//   c2e2c      cell across c2e[c][i]; s = +1 where c is the edge's first cell
+//   v2e[v]     counter-clockwise from the smallest incident edge id, -1 pad
+//   v2c[v][i]  cell between v2e[v][i] and v2e[v][i+1]
+//   e2c2e[e]   other edges of c0 then of c1, in c2e order
+//   e2c2v[e]   v0, v1, vertex of c0 off e, vertex of c1 off e
+// Morton renumbering: cells by (key, id), key interleaving
+// q(u) = floor((u + 1) * 0.5 * (2^21 - 1)) of the unit circumcentre with x in
+// the top bit of each triple; edges by (min new cell, max new cell, id);
+// vertices by (min new id of their cells, id).
+// This file is compiled without floating-point contraction so that the
+// floating-point decisions above (orientation tests, Morton quantisation)
+// are taken exactly as written.
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace dc {
+
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 ld(const std::vector<double>& a, int i) { return {a[3 * i], a[3 * i + 1], a[3 * i + 2]}; }
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 scl(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+
+uint64_t morton(V3 u) {
+  const double c[3] = {u.x, u.y, u.z};
+  uint64_t q[3];
+  for (int a = 0; a < 3; ++a) q[a] = (uint64_t)std::floor((c[a] + 1.0) * 0.5 * 2097151.0);
+  uint64_t key = 0;
+  for (int bit = 0; bit < 21; ++bit) {
+    key |= ((q[0] >> bit) & 1ull) << (3 * bit + 2);
+    key |= ((q[1] >> bit) & 1ull) << (3 * bit + 1);
+    key |= ((q[2] >> bit) & 1ull) << (3 * bit + 0);
+  }
+  return key;
+}
+
+bool finite_pos(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!(std::isfinite(a[i]) && a[i] > 0.0)) return false;
+  return true;
+}
+bool finite_all(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+void lsq_vertex_weights(const HostGrid& g, int v, double w[3][6]) {
+  // V = P (N P)^+ vn: least-squares fit of the normal winds of the incident
+  // edges by a vector tangent to the sphere at the vertex.
+  V3 x = ld(g.xv, v);
+  V3 ax = std::fabs(x.x) < 0.9 ? V3{1, 0, 0} : V3{0, 1, 0};
+  V3 e1 = cross(ax, x);
+  e1 = scl(e1, 1.0 / norm(e1));
+  V3 e2 = cross(x, e1);
+  double np[6][2] = {};
+  for (int s = 0; s < 6; ++s) {
+    int e = g.v2e[6 * v + s];
+    if (e < 0) continue;
+    V3 n = ld(g.nrm, e);
+    np[s][0] = dot(n, e1);
+    np[s][1] = dot(n, e2);
+  }
+  double a = 0, b = 0, c = 0;  // G = (NP)^T (NP) = [[a b][b c]]
+  for (int s = 0; s < 6; ++s) {
+    a += np[s][0] * np[s][0];
+    b += np[s][0] * np[s][1];
+    c += np[s][1] * np[s][1];
+  }
+  const double det = a * c - b * b;
+  const double i00 = c / det, i01 = -b / det, i11 = a / det;
+  for (int s = 0; s < 6; ++s) {
+    const double p0 = i00 * np[s][0] + i01 * np[s][1];
+    const double p1 = i01 * np[s][0] + i11 * np[s][1];
+    w[0][s] = e1.x * p0 + e2.x * p1;
+    w[1][s] = e1.y * p0 + e2.y * p1;
+    w[2][s] = e1.z * p0 + e2.z * p1;
+  }
+}
+
+int build_host_grid(const dc_grid_desc* D, HostGrid* g, std::string* err) {
+  auto fail = [&](int code, const std::string& m) {
+    *err = m;
+    return code;
+  };
+  if (!D) return fail(DC_EINVAL, "grid description is NULL");
+  const int nc = D->n_cells, ne = D->n_edges, nv = D->n_verts, K = D->n_lev;
+  if (nc <= 0 || ne <= 0 || nv <= 0 || K < 1) return fail(DC_EINVAL, "entity counts must be > 0 and n_lev >= 1");
+  if (nc > (1 << 28) || ne > (1 << 28) || nv > (1 << 28) || K > 4096) return fail(DC_EINVAL, "grid too large");
+  if (!D->e2c || !D->c2e || !D->e2v || !D->c2e2c || !D->vert_xyz || !D->cell_xyz || !D->edge_xyz ||
+      !D->edge_length || !D->dual_edge_length || !D->cell_area || !D->dual_area || !D->edge_normal_xyz ||
+      !D->z_half || !D->exner_ref_full || !D->theta_ref_full || !D->theta_ref_half || !D->dexner_dz_ref_half)
+    return fail(DC_EINVAL, "a grid description pointer is NULL");
+  if (!(D->radius > 0.0) || !std::isfinite(D->radius)) return fail(DC_EINVAL, "radius must be > 0");
+  if (D->sfc_reorder != 0 && D->sfc_reorder != 1) return fail(DC_EINVAL, "sfc_reorder must be 0 or 1");
+
+  // ---- validation of the given tables (original numbering) ----
+  for (int i = 0; i < 2 * ne; ++i)
+    if (D->e2c[i] < 0 || D->e2c[i] >= nc) return fail(DC_EGRID, "e2c index out of range");
+  for (int i = 0; i < 2 * ne; ++i)
+    if (D->e2v[i] < 0 || D->e2v[i] >= nv) return fail(DC_EGRID, "e2v index out of range");
+  for (int i = 0; i < 3 * nc; ++i)
+    if (D->c2e[i] < 0 || D->c2e[i] >= ne) return fail(DC_EGRID, "c2e index out of range");
+  for (int i = 0; i < 3 * nc; ++i)
+    if (D->c2e2c[i] < 0 || D->c2e2c[i] >= nc) return fail(DC_EGRID, "c2e2c index out of range");
+  if ((long long)nv - ne + nc != 2) return fail(DC_EGRID, "Euler characteristic V - E + C != 2");
+  for (int e = 0; e < ne; ++e) {
+    if (D->e2c[2 * e] == D->e2c[2 * e + 1]) return fail(DC_EGRID, "edge with identical cells");
+    if (D->e2v[2 * e] == D->e2v[2 * e + 1]) return fail(DC_EGRID, "edge with identical vertices");
+  }
+  {
+    std::vector<int> cnt(ne, 0);
+    for (int c = 0; c < nc; ++c)
+      for (int i = 0; i < 3; ++i) {
+        const int e = D->c2e[3 * c + i];
+        if (D->e2c[2 * e] != c && D->e2c[2 * e + 1] != c) return fail(DC_EGRID, "c2e and e2c disagree");
+        cnt[e]++;
+      }
+    for (int e = 0; e < ne; ++e)
+      if (cnt[e] != 2) return fail(DC_EGRID, "an edge is not in exactly two cells");
+    for (int c = 0; c < nc; ++c) {
+      int across[3], given[3];
+      for (int i = 0; i < 3; ++i) {
+        const int e = D->c2e[3 * c + i];
+        across[i] = D->e2c[2 * e] == c ? D->e2c[2 * e + 1] : D->e2c[2 * e];
+        given[i] = D->c2e2c[3 * c + i];
+      }
+      std::sort(across, across + 3);
+      std::sort(given, given + 3);
+      if (!std::equal(across, across + 3, given)) return fail(DC_EGRID, "c2e2c disagrees with c2e/e2c");
+      // the three edges must close a triangle: 3 distinct vertices, each on 2 edges
+      int vs[6];
+      for (int i = 0; i < 3; ++i) {
+        const int e = D->c2e[3 * c + i];
+        vs[2 * i] = D->e2v[2 * e];
+        vs[2 * i + 1] = D->e2v[2 * e + 1];
+      }
+      std::sort(vs, vs + 6);
+      if (!(vs[0] == vs[1] && vs[2] == vs[3] && vs[4] == vs[5] && vs[1] != vs[2] && vs[3] != vs[4]))
+        return fail(DC_EGRID, "the edges of a cell do not form a triangle");
+    }
+  }
+  if (!finite_pos(D->edge_length, ne) || !finite_pos(D->dual_edge_length, ne) || !finite_pos(D->cell_area, nc) ||
+      !finite_pos(D->dual_area, nv))
+    return fail(DC_EGRID, "lengths and areas must be finite and > 0");
+  if (!finite_all(D->vert_xyz, 3 * (size_t)nv) || !finite_all(D->cell_xyz, 3 * (size_t)nc) ||
+      !finite_all(D->edge_xyz, 3 * (size_t)ne) || !finite_all(D->edge_normal_xyz, 3 * (size_t)ne))
+    return fail(DC_EGRID, "positions and normals must be finite");
+  for (int e = 0; e < ne; ++e) {
+    V3 n{D->edge_normal_xyz[3 * e], D->edge_normal_xyz[3 * e + 1], D->edge_normal_xyz[3 * e + 2]};
+    const int c0 = D->e2c[2 * e], c1 = D->e2c[2 * e + 1];
+    V3 x0{D->cell_xyz[3 * c0], D->cell_xyz[3 * c0 + 1], D->cell_xyz[3 * c0 + 2]};
+    V3 x1{D->cell_xyz[3 * c1], D->cell_xyz[3 * c1 + 1], D->cell_xyz[3 * c1 + 2]};
+    if (!(dot(n, sub(x1, x0)) > 0.0)) return fail(DC_EGRID, "edge normal does not point from e2c[0] to e2c[1]");
+  }
+  if (!finite_all(D->z_half, K + 1)) return fail(DC_EGRID, "z_half must be finite");
+  for (int k = 0; k < K; ++k)
+    if (!(D->z_half[k] > D->z_half[k + 1])) return fail(DC_EGRID, "z_half must decrease strictly (level 0 = top)");
+  if (!finite_pos(D->exner_ref_full, K) || !finite_pos(D->theta_ref_full, K) || !finite_pos(D->theta_ref_half, K + 1) ||
+      !finite_all(D->dexner_dz_ref_half, K + 1))
+    return fail(DC_EGRID, "reference profiles must be finite (and positive for Exner and theta)");
+
+  g->nc = nc;
+  g->ne = ne;
+  g->nv = nv;
+  g->K = K;
+  g->radius = D->radius;
+  g->mean_area = 4.0 * M_PI * D->radius * D->radius / nc;
+
+  // ---- optional Morton renumbering (permutations internal -> original) ----
+  std::vector<int32_t> pc(nc), pe(ne), pv(nv);
+  std::iota(pc.begin(), pc.end(), 0);
+  std::iota(pe.begin(), pe.end(), 0);
+  std::iota(pv.begin(), pv.end(), 0);
+  if (D->sfc_reorder) {
+    std::vector<uint64_t> key(nc);
+    for (int c = 0; c < nc; ++c) key[c] = morton({D->cell_xyz[3 * c], D->cell_xyz[3 * c + 1], D->cell_xyz[3 * c + 2]});
+    std::stable_sort(pc.begin(), pc.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<int32_t> oc(nc);
+    for (int i = 0; i < nc; ++i) oc[pc[i]] = i;
+    std::vector<int32_t> lo(ne), hi(ne);
+    for (int e = 0; e < ne; ++e) {
+      const int a = oc[D->e2c[2 * e]], b = oc[D->e2c[2 * e + 1]];
+      lo[e] = std::min(a, b);
+      hi[e] = std::max(a, b);
+    }
+    std::stable_sort(pe.begin(), pe.end(), [&](int a, int b) { return lo[a] != lo[b] ? lo[a] < lo[b] : hi[a] < hi[b]; });
+    std::vector<int32_t> vmin(nv, INT32_MAX);
+    for (int c = 0; c < nc; ++c)
+      for (int i = 0; i < 3; ++i) {
+        const int e = D->c2e[3 * c + i];
+        for (int j = 0; j < 2; ++j) {
+          const int v = D->e2v[2 * e + j];
+          vmin[v] = std::min(vmin[v], oc[c]);
+        }
+      }
+    std::stable_sort(pv.begin(), pv.end(), [&](int a, int b) { return vmin[a] < vmin[b]; });
+  }
+  std::vector<int32_t> oc(nc), oe(ne), ov(nv);
+  for (int i = 0; i < nc; ++i) oc[pc[i]] = i;
+  for (int i = 0; i < ne; ++i) oe[pe[i]] = i;
+  for (int i = 0; i < nv; ++i) ov[pv[i]] = i;
+  g->perm_c = pc;
+  g->perm_e = pe;
+  g->perm_v = pv;
+
+  // renumbered inputs and geometry
+  std::vector<int32_t> e2c(2 * ne), e2v_in(2 * ne), c2e_in(3 * nc);
+  for (int e = 0; e < ne; ++e)
+    for (int j = 0; j < 2; ++j) {
+      e2c[2 * e + j] = oc[D->e2c[2 * pe[e] + j]];
+      e2v_in[2 * e + j] = ov[D->e2v[2 * pe[e] + j]];
+    }
+  for (int c = 0; c < nc; ++c)
+    for (int i = 0; i < 3; ++i) c2e_in[3 * c + i] = oe[D->c2e[3 * pc[c] + i]];
+  g->xv.resize(3 * nv);
+  g->xe.resize(3 * ne);
+  g->xc.resize(3 * nc);
+  g->nrm.resize(3 * ne);
+  g->tan.resize(3 * ne);
+  g->l.resize(ne);
+  g->d.resize(ne);
+  g->ac.resize(nc);
+  g->av.resize(nv);
+  for (int v = 0; v < nv; ++v) {
+    for (int j = 0; j < 3; ++j) g->xv[3 * v + j] = D->vert_xyz[3 * pv[v] + j];
+    g->av[v] = D->dual_area[pv[v]];
+  }
+  for (int c = 0; c < nc; ++c) {
+    for (int j = 0; j < 3; ++j) g->xc[3 * c + j] = D->cell_xyz[3 * pc[c] + j];
+    g->ac[c] = D->cell_area[pc[c]];
+  }
+  for (int e = 0; e < ne; ++e) {
+    for (int j = 0; j < 3; ++j) {
+      g->xe[3 * e + j] = D->edge_xyz[3 * pe[e] + j];
+      g->nrm[3 * e + j] = D->edge_normal_xyz[3 * pe[e] + j];
+    }
+    g->l[e] = D->edge_length[pe[e]];
+    g->d[e] = D->dual_edge_length[pe[e]];
+  }
+
+  // ---- canonical tables ----
+  g->e2c = e2c;
+  g->e2v.resize(2 * ne);
+  for (int e = 0; e < ne; ++e) {
+    V3 t = cross(ld(g->xe, e), ld(g->nrm, e));
+    g->tan[3 * e] = t.x;
+    g->tan[3 * e + 1] = t.y;
+    g->tan[3 * e + 2] = t.z;
+    const int a = e2v_in[2 * e], b = e2v_in[2 * e + 1];
+    const double along = dot(sub(ld(g->xv, b), ld(g->xv, a)), t);
+    g->e2v[2 * e] = along > 0 ? a : b;
+    g->e2v[2 * e + 1] = along > 0 ? b : a;
+  }
+  auto common = [&](int ea, int eb) {
+    const int a0 = g->e2v[2 * ea], a1 = g->e2v[2 * ea + 1];
+    return (a0 == g->e2v[2 * eb] || a0 == g->e2v[2 * eb + 1]) ? a0 : a1;
+  };
+  g->c2e.resize(3 * nc);
+  g->c2v.resize(3 * nc);
+  g->c2e2c.resize(3 * nc);
+  g->sgn_c.resize(3 * nc);
+  for (int c = 0; c < nc; ++c) {
+    int ce[3] = {c2e_in[3 * c], c2e_in[3 * c + 1], c2e_in[3 * c + 2]};
+    int cv[3];
+    for (int i = 0; i < 3; ++i) cv[i] = common(ce[(i + 2) % 3], ce[i]);
+    V3 a = ld(g->xv, cv[0]), b = ld(g->xv, cv[1]), cc = ld(g->xv, cv[2]);
+    if (!(dot(cross(sub(b, a), sub(cc, a)), ld(g->xc, c)) > 0)) {
+      std::swap(ce[1], ce[2]);
+      for (int i = 0; i < 3; ++i) cv[i] = common(ce[(i + 2) % 3], ce[i]);
+    }
+    for (int i = 0; i < 3; ++i) {
+      g->c2e[3 * c + i] = ce[i];
+      g->c2v[3 * c + i] = cv[i];
+      const bool first = e2c[2 * ce[i]] == c;
+      g->c2e2c[3 * c + i] = first ? e2c[2 * ce[i] + 1] : e2c[2 * ce[i]];
+      g->sgn_c[3 * c + i] = first ? 1 : -1;
+    }
+  }
+  // counter-clockwise walk around each vertex
+  std::vector<int32_t> nxt_e(2 * ne, -1), nxt_c(2 * ne, -1);
+  for (int c = 0; c < nc; ++c)
+    for (int i = 0; i < 3; ++i) {
+      const int v = g->c2v[3 * c + i];
+      const int ef = g->c2e[3 * c + i];
+      const int side = g->e2v[2 * ef] != v ? 1 : 0;
+      nxt_e[2 * ef + side] = g->c2e[3 * c + (i + 2) % 3];
+      nxt_c[2 * ef + side] = c;
+    }
+  std::vector<int32_t> emin(nv, INT32_MAX);
+  for (int e = 0; e < ne; ++e)
+    for (int j = 0; j < 2; ++j) emin[g->e2v[2 * e + j]] = std::min(emin[g->e2v[2 * e + j]], e);
+  g->v2e.assign(6 * (size_t)nv, -1);
+  g->v2c.assign(6 * (size_t)nv, -1);
+  g->sgn_v.assign(6 * (size_t)nv, 0);
+  for (int v = 0; v < nv; ++v) {
+    int cur = emin[v];
+    if (cur == INT32_MAX) return fail(DC_EGRID, "vertex without edges");
+    bool closed = false;
+    for (int i = 0; i < 6; ++i) {
+      g->v2e[6 * v + i] = cur;
+      g->sgn_v[6 * v + i] = g->e2v[2 * cur + 1] == v ? 1 : -1;
+      const int side = g->e2v[2 * cur] != v ? 1 : 0;
+      const int nx = nxt_e[2 * cur + side];
+      g->v2c[6 * v + i] = nxt_c[2 * cur + side];
+      if (nx < 0) return fail(DC_EGRID, "open vertex fan (inconsistent orientation)");
+      cur = nx;
+      if (cur == emin[v]) {
+        closed = true;
+        if (i < 2) return fail(DC_EGRID, "vertex with fewer than 3 edges");
+        break;
+      }
+    }
+    if (!closed) return fail(DC_EGRID, "a vertex has more than 6 edges");
+  }
+  g->e2c2e.resize(4 * ne);
+  g->e2c2v.resize(4 * ne);
+  for (int e = 0; e < ne; ++e) {
+    g->e2c2v[4 * e] = g->e2v[2 * e];
+    g->e2c2v[4 * e + 1] = g->e2v[2 * e + 1];
+    for (int side = 0; side < 2; ++side) {
+      const int c = e2c[2 * e + side];
+      int m = 0;
+      for (int i = 0; i < 3; ++i) {
+        const int x = g->c2e[3 * c + i];
+        if (x != e) g->e2c2e[4 * e + 2 * side + (m++)] = x;
+        const int vv = g->c2v[3 * c + i];
+        if (vv != g->e2v[2 * e] && vv != g->e2v[2 * e + 1]) g->e2c2v[4 * e + 2 + side] = vv;
+      }
+      if (m != 2) return fail(DC_EGRID, "edge not found in its cell");
+    }
+  }
+
+  // ---- vertical column ----
+  g->z_half.assign(D->z_half, D->z_half + K + 1);
+  g->ex_ref.assign(D->exner_ref_full, D->exner_ref_full + K);
+  g->th_ref.assign(D->theta_ref_full, D->theta_ref_full + K);
+  g->th_ref_ic.assign(D->theta_ref_half, D->theta_ref_half + K + 1);
+  g->dex_ref_ic.assign(D->dexner_dz_ref_half, D->dexner_dz_ref_half + K + 1);
+  const int K1 = K + 1;
+  g->vert.assign((size_t)VT_COUNT * K1, 0.0);
+  std::vector<double> zf(K);
+  for (int j = 0; j < K; ++j) zf[j] = 0.5 * (g->z_half[j] + g->z_half[j + 1]);
+  for (int j = 0; j < K; ++j) {
+    const double dz = g->z_half[j] - g->z_half[j + 1];
+    g->vert[VT_DZF * K1 + j] = dz;
+    g->vert[VT_IDZF * K1 + j] = 1.0 / dz;
+    g->vert[VT_EXREF * K1 + j] = g->ex_ref[j];
+    g->vert[VT_THREF * K1 + j] = g->th_ref[j];
+  }
+  for (int k = 0; k <= K; ++k) {
+    g->vert[VT_THREFIC * K1 + k] = g->th_ref_ic[k];
+    g->vert[VT_DEXREFIC * K1 + k] = g->dex_ref_ic[k];
+    if (k >= 1 && k <= K - 1) {
+      g->vert[VT_IDZH * K1 + k] = 1.0 / (zf[k - 1] - zf[k]);
+      g->vert[VT_IDZC2 * K1 + k] = 1.0 / (g->z_half[k - 1] - g->z_half[k + 1]);
+    }
+  }
+
+  // ---- stencil coefficients (slot-major, padded) ----
+  const int cs = pad_to(nc, kPad), es = pad_to(ne, kPad), vs = pad_to(nv, kPad);
+  g->cs = cs;
+  g->es = es;
+  g->vs = vs;
+  const double R = g->radius;
+  g->t_c2e.assign(3 * (size_t)cs, 0);
+  g->t_c2e2c.assign(3 * (size_t)cs, 0);
+  g->k_div.assign(3 * (size_t)cs, 0.0);
+  g->k_lap.assign(3 * (size_t)cs, 0.0);
+  g->k_area.assign(cs, 0.0);
+  for (int c = 0; c < nc; ++c) {
+    g->k_area[c] = g->ac[c];
+    for (int i = 0; i < 3; ++i) {
+      const int e = g->c2e[3 * c + i];
+      g->t_c2e[i * cs + c] = e;
+      g->t_c2e2c[i * cs + c] = g->c2e2c[3 * c + i];
+      g->k_div[i * cs + c] = g->sgn_c[3 * c + i] * g->l[e] / g->ac[c];
+      g->k_lap[i * cs + c] = g->l[e] / (g->d[e] * g->ac[c]);
+    }
+  }
+  g->t_e2c.assign(2 * (size_t)es, 0);
+  g->t_e2v.assign(2 * (size_t)es, 0);
+  g->t_e2c2e.assign(4 * (size_t)es, 0);
+  g->t_e2c2v.assign(4 * (size_t)es, 0);
+  g->k_vt.assign(5 * (size_t)es, 0.0);
+  g->k_invd.assign(es, 0.0);
+  g->k_invl.assign(es, 0.0);
+  g->k_f.assign(es, 0.0);
+  g->k_ae.assign(es, 0.0);
+  g->k_invlr.assign(es, 0.0);
+  g->k_nrm.assign(3 * (size_t)es, 0.0);
+  g->k_tan.assign(3 * (size_t)es, 0.0);
+  for (int e = 0; e < ne; ++e) {
+    for (int j = 0; j < 2; ++j) {
+      g->t_e2c[j * es + e] = e2c[2 * e + j];
+      g->t_e2v[j * es + e] = g->e2v[2 * e + j];
+    }
+    for (int j = 0; j < 4; ++j) {
+      g->t_e2c2e[j * es + e] = g->e2c2e[4 * e + j];
+      g->t_e2c2v[j * es + e] = g->e2c2v[4 * e + j];
+    }
+    const V3 t = ld(g->tan, e);
+    // Perot: vt_e = 1/2 (V_c0 + V_c1) . t_e, V_c = (1/A_c) sum_i s l F (x_ei - x_c) R
+    double self = 0.0;
+    for (int side = 0; side < 2; ++side) {
+      const int c = e2c[2 * e + side];
+      int m = 0;
+      for (int i = 0; i < 3; ++i) {
+        const int x = g->c2e[3 * c + i];
+        const double coef = 0.5 * (g->sgn_c[3 * c + i] * g->l[x] / g->ac[c]) * R * dot(sub(ld(g->xe, x), ld(g->xc, c)), t);
+        if (x == e)
+          self += coef;
+        else
+          g->k_vt[(1 + 2 * side + (m++)) * es + e] = coef;
+      }
+    }
+    g->k_vt[e] = self;
+    g->k_invd[e] = 1.0 / g->d[e];
+    g->k_invl[e] = 1.0 / g->l[e];
+    g->k_f[e] = 0.0;  // set per state (depends on omega)
+    g->k_ae[e] = 0.5 * g->l[e] * g->d[e];
+    const V3 x2 = ld(g->xv, g->e2c2v[4 * e + 2]), x3 = ld(g->xv, g->e2c2v[4 * e + 3]);
+    g->k_invlr[e] = 1.0 / (R * std::atan2(norm(cross(x2, x3)), dot(x2, x3)));
+    for (int j = 0; j < 3; ++j) {
+      g->k_nrm[j * es + e] = g->nrm[3 * e + j];
+      g->k_tan[j * es + e] = g->tan[3 * e + j];
+    }
+  }
+  g->t_v2e.assign(6 * (size_t)vs, 0);
+  g->k_curl.assign(6 * (size_t)vs, 0.0);
+  g->k_lsq.assign(18 * (size_t)vs, 0.0);
+  for (int v = 0; v < nv; ++v) {
+    double w[3][6];
+    lsq_vertex_weights(*g, v, w);
+    for (int s = 0; s < 6; ++s) {
+      const int e = g->v2e[6 * v + s];
+      g->t_v2e[s * vs + v] = e >= 0 ? e : g->v2e[6 * v];
+      g->k_curl[s * vs + v] = e >= 0 ? g->sgn_v[6 * v + s] * g->d[e] / g->av[v] : 0.0;
+      for (int j = 0; j < 3; ++j) g->k_lsq[(j * 6 + s) * vs + v] = e >= 0 ? w[j][s] : 0.0;
+    }
+  }
+  return DC_OK;
+}
+
+}  // namespace dc

@@ -1,0 +1,62 @@
+// Internal declarations of the dycore library (not part of the public ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dycore.h"
+
+namespace dc {
+
+constexpr int kPad = 64;  // level stride granularity (entities)
+
+inline int pad_to(int n, int m) { return (n + m - 1) / m * m; }
+
+// Host-side grid: renumbered inputs, canonical tables, geometry and the
+// stencil coefficients in slot-major ("SoA") layout with padded strides.
+struct HostGrid {
+  int nc = 0, ne = 0, nv = 0, K = 0;
+  int cs = 0, es = 0, vs = 0;  // padded strides
+  double radius = 0.0, mean_area = 0.0;
+  // canonical tables, row-major [entity][slot] (what dc_grid_table returns)
+  std::vector<int32_t> e2c, c2e, e2v, c2e2c, c2v, v2e, v2c, e2c2e, e2c2v;
+  std::vector<int32_t> perm_c, perm_e, perm_v;  // internal id -> original id
+  std::vector<int32_t> sgn_c, sgn_v;            // [C][3], [V][6]
+  // geometry in internal numbering
+  std::vector<double> xv, xe, xc, nrm, tan;     // [.][3]
+  std::vector<double> l, d, ac, av;
+  // vertical column
+  std::vector<double> z_half, ex_ref, th_ref, th_ref_ic, dex_ref_ic;
+  // stencil coefficients, slot-major with padded strides
+  std::vector<int32_t> t_c2e, t_c2e2c;            // [3][cs]
+  std::vector<double> k_div, k_lap, k_area;       // [3][cs], [3][cs], [cs]
+  std::vector<int32_t> t_e2c, t_e2v, t_e2c2e, t_e2c2v;  // [2][es], [2][es], [4][es], [4][es]
+  std::vector<double> k_vt;                       // [5][es] self, e2c2e[0..3]
+  std::vector<double> k_invd, k_invl, k_f, k_ae, k_invlr;  // [es]
+  std::vector<double> k_nrm, k_tan;               // [3][es]
+  std::vector<int32_t> t_v2e;                     // [6][vs] (pentagon slot 5 -> slot 0)
+  std::vector<double> k_curl;                     // [6][vs] (0 in pentagon slot 5)
+  std::vector<double> k_lsq;                      // [18][vs] row j*6+s: component j, slot s
+  std::vector<double> vert;                       // vertical tables, see VertTab
+};
+
+// Offsets (in units of K+1 doubles) of the per-level vertical tables.
+enum VertTab {
+  VT_DZF = 0,    // dz_full[j]
+  VT_IDZF,       // 1/dz_full[j]
+  VT_IDZH,       // 1/(z_full[k-1]-z_full[k]), interior half levels
+  VT_IDZC2,      // 1/(z_half[k-1]-z_half[k+1]), interior half levels
+  VT_EXREF,      // pi0 full
+  VT_THREF,      // theta0 full
+  VT_THREFIC,    // theta0 half
+  VT_DEXREFIC,   // d pi0/dz half
+  VT_COUNT
+};
+
+int build_host_grid(const dc_grid_desc* desc, HostGrid* g, std::string* err);
+void lsq_vertex_weights(const HostGrid& g, int v, double w[3][6]);
+
+void set_error(const std::string& msg);
+
+}  // namespace dc

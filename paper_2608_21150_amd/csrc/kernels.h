@@ -1,0 +1,109 @@
+// Device-side views and kernel launchers of the dycore library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+namespace dc {
+
+// Kernel identifiers for per-launch timing.
+enum KernelId {
+  K_CURL_P = 0, K_VT_P, K_CELL_P, K_EDGE_P, K_COL_P,
+  K_CURL_C, K_VT_C, K_CELL_C, K_EDGE_C, K_COL_C,
+  K_DVERT, K_DDIV, K_DEDGE1, K_DCV2, K_DEDGE2,
+  K_COUNT
+};
+extern const char* const kKernelNames[K_COUNT];
+
+// Optional HIP-event timer: mark(id) before a launch, mark(-1) after it.
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kid;
+  size_t used = 0;
+  void mark(hipStream_t s, int id) {
+    if (!on) return;
+    if (used == ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+      ev.push_back(e);
+      kid.push_back(0);
+    }
+    kid[used] = id;
+    (void)hipEventRecord(ev[used], s);
+    ++used;
+  }
+};
+
+// Read-only grid view handed to every kernel by value.  Tables are
+// slot-major ([slot][entity]) with padded strides so that neighbouring
+// threads read neighbouring table entries.
+struct DevGrid {
+  int nc, ne, nv, K, cs, es, vs;
+  const int* c2e;       // [3][cs]
+  const int* c2e2c;     // [3][cs]
+  const double* kdiv;   // [3][cs]  s l / A_c
+  const double* klap;   // [3][cs]  l / (d A_c)
+  const double* area;   // [cs]
+  const int* e2c;       // [2][es]
+  const int* e2v;       // [2][es]  ordered along the tangent
+  const int* e2c2e;     // [4][es]
+  const int* e2c2v;     // [4][es]
+  const double* kvt;    // [5][es]  tangential-wind weights: self, e2c2e[0..3]
+  const double* invd;   // [es] 1/d_e
+  const double* invl;   // [es] 1/l_e
+  const double* ae;     // [es] l_e d_e / 2
+  const double* invlr;  // [es] 1/(rhombus diagonal length)
+  const double* nrm;    // [3][es]
+  const double* tan;    // [3][es]
+  const int* v2e;       // [6][vs]
+  const double* kcurl;  // [6][vs] sig d / A_v
+  const double* klsq;   // [18][vs]
+  const double* vert;   // [VT_COUNT][K+1]
+  const double* fe;     // [es] Coriolis parameter (per state)
+  const double* tau;    // [K+1] sponge rate (per state)
+};
+
+// Launch geometry of a level-blocked stencil kernel.
+struct Tile {
+  int threads;  // threads per block (entities)
+  int kb;       // levels per block
+};
+
+struct StepCoef {
+  double dtau, dt, eta, a0, a1, cpd, rd_cvd, cvd_rd, c4a2, cs, cap, k4;
+  int diffuse_w;
+};
+
+// Pointers of one predictor/corrector/diffusion pass; the meaning of each
+// member is given at the launcher that uses it.
+template <typename R>
+struct Bufs {
+  // state at the start of the substep
+  const R* vn;
+  const double *w, *rho, *ex, *th;
+  // workspace
+  R *vt, *tvn0, *vns, *kc, *tw0, *tw1, *d2, *zeta, *vv;
+  double *ws, *cp, *dp, *drx, *dxx, *wtmp;
+  // outputs of the corrector
+  R* vn_out;
+  double *w_out, *rho_out, *ex_out, *th_out;
+};
+
+template <typename R>
+void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* tiles, hipStream_t s,
+                    Prof* prof);
+template <typename R>
+void launch_diffusion(const DevGrid& g, R* vn, const double* w_in, double* w_out, R* vt_l1, R* nu, R* kc_div,
+                      R* d2_divl1, R* zeta, R* vv, const StepCoef& c, const Tile* tiles, hipStream_t s,
+                      Prof* prof);
+template <typename R>
+void launch_diag(const DevGrid& g, const R* vn, const double* w, const double* rho, const double* th,
+                 const double* ex, double* partial, double* out, hipStream_t s);
+int diag_partial_count(const DevGrid& g);
+
+// indices into the tile table
+enum TileId { T_CURL = 0, T_VT, T_CELLADV, T_EDGE, T_COL, T_DVERT, T_DCELL, T_DEDGE, T_COUNT };
+
+}  // namespace dc

@@ -1,0 +1,271 @@
+"""Thin ctypes binding of libdycore.so (argument marshalling only).
+
+Every step of the time step runs in the library's HIP kernels; PyTorch only
+provides device memory (the borrowed field buffers and the workspace) and the
+current HIP stream.  Importing this module fails loudly when the library is
+not built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdycore.so")
+
+DC_OK, DC_EINVAL, DC_EGRID, DC_EHIP, DC_ENOMEM, DC_ENONFINITE, DC_EBUSY, DC_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+PREC = {"fp64": 0, "mixed": 1}
+DIFF = {"plain": 0, "surrogate": 1, "none": 2}
+FIELDS = ("vn", "w", "rho", "exner", "theta_v")
+TABLES = ("e2c", "c2e", "e2v", "c2e2c", "c2v", "v2e", "v2c", "e2c2e", "e2c2v", "perm_cell", "perm_edge", "perm_vert")
+
+_p = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("n_verts", ctypes.c_int32), ("n_lev", ctypes.c_int32),
+        ("e2c", _i32p), ("c2e", _i32p), ("e2v", _i32p), ("c2e2c", _i32p),
+        ("vert_xyz", _f64p), ("cell_xyz", _f64p), ("edge_xyz", _f64p),
+        ("edge_length", _f64p), ("dual_edge_length", _f64p),
+        ("cell_area", _f64p), ("dual_area", _f64p),
+        ("edge_normal_xyz", _f64p),
+        ("z_half", _f64p),
+        ("exner_ref_full", _f64p), ("theta_ref_full", _f64p),
+        ("theta_ref_half", _f64p), ("dexner_dz_ref_half", _f64p),
+        ("radius", ctypes.c_double),
+        ("sfc_reorder", ctypes.c_int32),
+    ]
+
+
+class GridInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("n_cells", "n_edges", "n_verts", "n_lev", "cell_stride", "edge_stride", "vert_stride")]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("eta", "adv_w0", "adv_w1", "divdamp_c4", "rayleigh_tau0", "rayleigh_zfrac", "smag_cs",
+                 "smag_cap", "hdiff_k4", "rd", "cpd", "cvd", "omega")] + [
+        ("diffuse_w", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
+
+
+class Fields(ctypes.Structure):
+    _fields_ = [(n, _p) for n in FIELDS]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("theta_mass", ctypes.c_double), ("max_abs_w", ctypes.c_double),
+                ("max_abs_vn", ctypes.c_double), ("n_nonfinite", ctypes.c_int64)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("calls", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or python -m paper_2608_21150_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "dc_last_error": (ctypes.c_char_p, []),
+        "dc_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
+        "dc_grid_create": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.POINTER(_p)]),
+        "dc_grid_info_get": (ctypes.c_int, [_p, ctypes.POINTER(GridInfo)]),
+        "dc_grid_table": (ctypes.c_int, [_p, ctypes.c_int32, _i32p, ctypes.c_size_t]),
+        "dc_grid_destroy": (ctypes.c_int, [_p]),
+        "dc_field_bytes": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+        "dc_state_workspace_bytes": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+        "dc_state_create": (ctypes.c_int, [_p, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int, Fields, Fields, _p,
+                                           ctypes.c_size_t, _p, ctypes.POINTER(_p)]),
+        "dc_state_current": (ctypes.c_int, [_p, ctypes.POINTER(ctypes.c_int32)]),
+        "dc_state_read": (ctypes.c_int, [_p, ctypes.c_int32, _f64p, ctypes.c_size_t]),
+        "dc_state_write": (ctypes.c_int, [_p, ctypes.c_int32, _f64p, ctypes.c_size_t]),
+        "dc_dycore_step": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
+        "dc_diag_conservation": (ctypes.c_int, [_p, ctypes.POINTER(Diag)]),
+        "dc_state_destroy": (ctypes.c_int, [_p]),
+        "dc_state_profile": (ctypes.c_int, [_p, ctypes.c_int32]),
+        "dc_state_profile_read": (ctypes.c_int, [_p, ctypes.POINTER(KernelStat), ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_int32)]),
+        "dc_ensemble_create": (ctypes.c_int, [ctypes.POINTER(_p), ctypes.c_int32, ctypes.POINTER(_p)]),
+        "dc_ensemble_step": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
+        "dc_ensemble_destroy": (ctypes.c_int, [_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class DycoreError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dycore error {code}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc != DC_OK:
+        raise DycoreError(rc, lib.dc_last_error().decode())
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    check(lib.dc_params_default(ctypes.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_i32p)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_f64p)
+
+
+class Grid:
+    """Host description of an icosahedral grid plus its vertical column."""
+
+    def __init__(self, grid: dict, vert: dict, sfc: bool = False):
+        keep = []
+
+        def I(name):
+            a, p = _i32(grid[name])
+            keep.append(a)
+            return p
+
+        def F(arr):
+            a, p = _f64(arr)
+            keep.append(a)
+            return p
+
+        d = GridDesc()
+        d.n_cells, d.n_edges, d.n_verts = grid["n_cells"], grid["n_edges"], grid["n_verts"]
+        d.n_lev = len(vert["z_half"]) - 1
+        d.e2c, d.c2e, d.e2v, d.c2e2c = I("e2c"), I("c2e"), I("e2v"), I("c2e2c")
+        for name in ("vert_xyz", "cell_xyz", "edge_xyz", "edge_length", "dual_edge_length", "cell_area",
+                     "dual_area", "edge_normal_xyz"):
+            setattr(d, name, F(grid[name]))
+        for name in ("z_half", "exner_ref_full", "theta_ref_full", "theta_ref_half", "dexner_dz_ref_half"):
+            setattr(d, name, F(vert[name]))
+        d.radius = grid["radius"]
+        d.sfc_reorder = 1 if sfc else 0
+        h = _p()
+        check(lib.dc_grid_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        info = GridInfo()
+        check(lib.dc_grid_info_get(h, ctypes.byref(info)))
+        self.info = {n: getattr(info, n) for n, _ in GridInfo._fields_}
+
+    def table(self, name: str) -> np.ndarray:
+        i = self.info
+        shape = {"e2c": (i["n_edges"], 2), "c2e": (i["n_cells"], 3), "e2v": (i["n_edges"], 2),
+                 "c2e2c": (i["n_cells"], 3), "c2v": (i["n_cells"], 3), "v2e": (i["n_verts"], 6),
+                 "v2c": (i["n_verts"], 6), "e2c2e": (i["n_edges"], 4), "e2c2v": (i["n_edges"], 4),
+                 "perm_cell": (i["n_cells"],), "perm_edge": (i["n_edges"],), "perm_vert": (i["n_verts"],)}[name]
+        out = np.empty(shape, dtype=np.int32)
+        check(lib.dc_grid_table(self.handle, TABLES.index(name), out.ctypes.data_as(_i32p), out.size))
+        return out
+
+    def close(self):
+        if self.handle:
+            check(lib.dc_grid_destroy(self.handle))
+            self.handle = None
+
+
+class State:
+    """A prognostic state on the GPU over torch-owned device buffers."""
+
+    def __init__(self, grid: Grid, precision: str = "fp64", diffusion: str = "plain", params: Params | None = None,
+                 device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.grid = grid
+        self.precision = precision
+        self.diffusion = diffusion
+        dev = torch.device(device if device is not None else "cuda")
+        self.device = dev
+        prec = PREC[precision]
+        self.bufs = []
+        for _ in range(2):
+            b = {}
+            for fi, name in enumerate(FIELDS):
+                nb = ctypes.c_size_t()
+                check(lib.dc_field_bytes(grid.handle, prec, fi, ctypes.byref(nb)))
+                b[name] = torch.zeros(nb.value, dtype=torch.uint8, device=dev)
+            self.bufs.append(b)
+        nb = ctypes.c_size_t()
+        check(lib.dc_state_workspace_bytes(grid.handle, prec, DIFF[diffusion], ctypes.byref(nb)))
+        self.workspace = torch.zeros(nb.value, dtype=torch.uint8, device=dev)
+        fa = Fields(*[self.bufs[0][n].data_ptr() for n in FIELDS])
+        fb = Fields(*[self.bufs[1][n].data_ptr() for n in FIELDS])
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self.stream = stream
+        self.params = params if params is not None else default_params()
+        h = _p()
+        check(lib.dc_state_create(grid.handle, ctypes.byref(self.params), prec, DIFF[diffusion], fa, fb,
+                                  self.workspace.data_ptr(), self.workspace.numel(), _p(stream.cuda_stream),
+                                  ctypes.byref(h)))
+        self.handle = h
+
+    def write(self, state: dict):
+        for fi, name in enumerate(FIELDS):
+            a, p = _f64(state[name])
+            check(lib.dc_state_write(self.handle, fi, p, a.size))
+
+    def read(self) -> dict:
+        K = self.grid.info["n_lev"]
+        nc, ne = self.grid.info["n_cells"], self.grid.info["n_edges"]
+        shapes = {"vn": (K, ne), "w": (K + 1, nc), "rho": (K, nc), "exner": (K, nc), "theta_v": (K, nc)}
+        out = {}
+        for fi, name in enumerate(FIELDS):
+            a = np.empty(shapes[name], dtype=np.float64)
+            check(lib.dc_state_read(self.handle, fi, a.ctypes.data_as(_f64p), a.size))
+            out[name] = a
+        return out
+
+    def step(self, dt: float, nsub: int):
+        check(lib.dc_dycore_step(self.handle, float(dt), int(nsub)))
+
+    def current(self) -> int:
+        w = ctypes.c_int32()
+        check(lib.dc_state_current(self.handle, ctypes.byref(w)))
+        return w.value
+
+    def diag(self) -> dict:
+        d = Diag()
+        check(lib.dc_diag_conservation(self.handle, ctypes.byref(d)))
+        return {n: getattr(d, n) for n, _ in Diag._fields_}
+
+    def profile(self, enable: bool):
+        check(lib.dc_state_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        arr = (KernelStat * 32)()
+        n = ctypes.c_int32()
+        check(lib.dc_state_profile_read(self.handle, arr, 32, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].calls, arr[i].total_ms) for i in range(n.value)}
+
+    def close(self):
+        if self.handle:
+            check(lib.dc_state_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,189 @@
+"""GPU parity of the HIP time step against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 results are not unique (fused multiply-add and summation
+order change the last bits), so fields are compared by relative L2 norm,
+<= 1e-11 after 10 steps of the R2B2 workload; fields whose reference is
+identically zero (the resting atmosphere) by max-abs <= 1e-13.  Integer
+tables are compared bit for bit elsewhere.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2608_21150_amd import dycore as D  # noqa: E402
+from oracle import dycore as O  # noqa: E402
+from oracle.constants import default_params  # noqa: E402
+from oracle.grid import Grid as OGrid  # noqa: E402
+from synth import build_workload, initial_state, make_grid  # noqa: E402
+
+FIELDS = ("vn", "w", "rho", "exner", "theta_v")
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def run_gpu(g0, vert, S, dt, nsub, steps, sfc=False, precision="fp64", diffusion="plain", params=None):
+    G = D.Grid(g0, vert, sfc=sfc)
+    st = D.State(G, precision=precision, diffusion=diffusion, params=params)
+    st.write(S)
+    for _ in range(steps):
+        st.step(dt, nsub)
+    out = st.read()
+    d = st.diag()
+    st.close()
+    G.close()
+    return out, d
+
+
+def run_oracle(g0, vert, S, dt, nsub, steps, diffuse=True):
+    g = OGrid(g0, vert)
+    wts = O.vertex_lsq_weights(g)
+    for _ in range(steps):
+        S = O.step(g, S, dt, nsub, default_params(), diffuse=diffuse, wts=wts)
+    return S, g
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    g0, S, vert, spec = build_workload("r2b2_k30")
+    ref, og = run_oracle(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"])
+    return g0, S, vert, spec, ref, og
+
+
+def test_rest_state_stays_at_rest():
+    g0, S, vert, spec = build_workload("r2b2_k30_rest")
+    out, d = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 10)
+    for k in FIELDS:
+        assert np.max(np.abs(out[k] - S[k])) <= 1e-13, k
+    assert d["n_nonfinite"] == 0
+
+
+@pytest.mark.parametrize("sfc", [False, True])
+def test_config1_parity_10_steps(cfg1, sfc):
+    g0, S, vert, spec, ref, _ = cfg1
+    out, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"], sfc=sfc)
+    errs = {k: rel_l2(out[k], ref[k]) for k in FIELDS}
+    print("rel L2 vs oracle:", errs)
+    for k in FIELDS:
+        assert errs[k] <= 1e-11, (k, errs[k])
+
+
+def test_single_substep_no_diffusion():
+    g0, S, vert, spec = build_workload("r2b2_k30")
+    out, _ = run_gpu(g0, vert, S, 120.0, 1, 1, diffusion="none")
+    ref, _ = run_oracle(g0, vert, S, 120.0, 1, 1, diffuse=False)
+    for k in FIELDS:
+        assert rel_l2(out[k], ref[k]) <= 1e-13, (k, rel_l2(out[k], ref[k]))
+
+
+@pytest.mark.parametrize("name", ["r1b0_k4", "r2b0_k1", "r2b1_k7"])
+def test_small_and_ragged_grids(name):
+    g0, S, vert, spec = build_workload(name)
+    out, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"])
+    ref, _ = run_oracle(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"])
+    for k in FIELDS:
+        if np.linalg.norm(ref[k]) == 0:
+            assert np.max(np.abs(out[k])) <= 1e-13, k
+        else:
+            assert rel_l2(out[k], ref[k]) <= 1e-11, (k, rel_l2(out[k], ref[k]))
+
+
+def test_conservation_diagnostics(cfg1):
+    g0, S, vert, spec, ref, og = cfg1
+    G = D.Grid(g0, vert)
+    st = D.State(G)
+    st.write(S)
+    d0 = st.diag()
+    o0 = O.diag(og, S)
+    assert abs(d0["mass"] / o0["mass"] - 1) < 1e-14
+    assert abs(d0["theta_mass"] / o0["theta_mass"] - 1) < 1e-14
+    assert d0["max_abs_vn"] == o0["max_abs_vn"]
+    for _ in range(10):
+        st.step(spec["dt"], spec["nsub"])
+    d1 = st.diag()
+    assert abs(d1["mass"] / d0["mass"] - 1) <= 1e-13
+    o1 = O.diag(og, ref)
+    assert abs(d1["theta_mass"] / o1["theta_mass"] - 1) < 1e-12
+    assert d1["n_nonfinite"] == 0
+    st.close()
+    G.close()
+
+
+def test_deterministic_and_buffer_flip():
+    g0, S, vert, spec = build_workload("r2b2_k30")
+    a, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 3)
+    b, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 3)
+    for k in FIELDS:
+        assert np.array_equal(a[k], b[k]), k
+    G = D.Grid(g0, vert)
+    st = D.State(G)
+    st.write(S)
+    assert st.current() == 0
+    st.step(spec["dt"], 5)
+    assert st.current() == 1
+    st.step(spec["dt"], 4)
+    assert st.current() == 1
+    st.close()
+    G.close()
+
+
+def test_checkpoint_resume_bitwise():
+    g0, S, vert, spec = build_workload("r2b2_k30")
+    full, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 10)
+    half, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 5)
+    resumed, _ = run_gpu(g0, vert, half, spec["dt"], spec["nsub"], 5)
+    for k in FIELDS:
+        assert np.array_equal(full[k], resumed[k]), k
+
+
+def test_r2b5_one_step_parity():
+    g0, S, vert, spec = build_workload("r2b5_k65")
+    out, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 1)
+    ref, _ = run_oracle(g0, vert, S, spec["dt"], spec["nsub"], 1)
+    errs = {k: rel_l2(out[k], ref[k]) for k in FIELDS}
+    print("R2B5 rel L2:", errs)
+    for k in FIELDS:
+        assert errs[k] <= 1e-11, (k, errs[k])
+
+
+def test_nonfinite_detection_and_errors():
+    g0, S, vert, spec = build_workload("r1b0_k4")
+    G = D.Grid(g0, vert)
+    st = D.State(G, params=D.default_params(check_finite=1))
+    bad = {k: v.copy() for k, v in S.items()}
+    bad["theta_v"][1, 3] = np.nan
+    st.write(bad)
+    assert st.diag()["n_nonfinite"] >= 1
+    with pytest.raises(D.DycoreError) as ei:
+        st.step(spec["dt"], spec["nsub"])
+    assert ei.value.code == D.DC_ENONFINITE
+    st.write(S)
+    with pytest.raises(D.DycoreError) as ei:
+        st.step(-1.0, 2)
+    assert ei.value.code == D.DC_EINVAL
+    with pytest.raises(D.DycoreError) as ei:
+        st.step(600.0, 0)
+    assert ei.value.code == D.DC_EINVAL
+    with pytest.raises(D.DycoreError) as ei:
+        G.close()
+    assert ei.value.code == D.DC_EBUSY
+    st.close()
+    G.close()
+
+
+def test_mixed_precision_error_vs_fp64():
+    g0, S, vert, spec = build_workload("r2b5_k65")
+    a, da = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 10)
+    b, db = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 10, precision="mixed")
+    errs = {k: rel_l2(b[k], a[k]) for k in FIELDS}
+    print("mixed vs fp64 after 10 steps:", errs, "mass rel drift", db["mass"] / da["mass"] - 1)
+    for k in ("vn", "rho", "exner", "theta_v"):
+        assert errs[k] <= 1e-4, (k, errs[k])
+    assert abs(db["mass"] / da["mass"] - 1) < 1e-12
