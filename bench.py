@@ -28,16 +28,12 @@ def kernel_bytes(C, E, V, K, r):
     the horizontal intermediates (8 FP64, 4 mixed); cell prognostics are 8."""
     KE, KV, KC, K1C = K * E, K * V, K * C, (K + 1) * C
     return {
-        "curl_pred": r * (KE + KV),
-        "vt_pred": r * 2 * KE,
-        "cell_adv_pred": r * 2 * KE + 8 * K1C + r * (KC + K1C),
-        "edge_pred": r * 2 * KE + r * KV + r * KC + 8 * K1C + 8 * 2 * KC + r * 2 * KE,
-        "column_pred": r * KE + 8 * K1C + r * K1C + 8 * 3 * KC + 8 * K1C,
-        "curl_corr": r * (KE + KV),
-        "vt_corr": r * 2 * KE,
-        "cell_adv_corr": r * 2 * KE + 8 * K1C + r * (KC + K1C + KC),
-        "edge_corr": r * 4 * KE + r * KV + r * 2 * KC + 8 * K1C + 8 * 2 * KC + r * KE,
-        "column_corr": r * KE + 8 * K1C + r * 2 * K1C + 8 * 3 * KC + 8 * (K1C + 3 * KC),
+        "vort_ke_pred": r * KE + r * (KV + KC),
+        "edge_pred": r * KE + r * KV + r * KC + 8 * K1C + 8 * 2 * KC + r * 2 * KE,
+        "column_pred": 2 * r * KE + 8 * K1C + 8 * 3 * KC + 8 * K1C,
+        "vort_ke_corr": r * KE + r * (KV + 2 * KC),
+        "edge_corr": r * 3 * KE + r * KV + r * 2 * KC + 8 * K1C + 8 * 2 * KC + r * KE,
+        "column_corr": 3 * r * KE + 2 * 8 * K1C + 8 * 3 * KC + 8 * (K1C + 3 * KC),
         "diff_vertex": r * KE + r * 4 * KV,
         "diff_div": r * KE + r * KC,
         "diff_edge1": r * KC + r * 4 * KV + r * 2 * KE,
@@ -104,6 +100,8 @@ def main():
     ap.add_argument("--sfc", type=int, default=-1, help="1/0 force the Morton renumbering; -1 workload default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -111,6 +109,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
 
     from paper_2608_21150_amd import dycore as D
     from synth import WORKLOADS, build_workload

@@ -49,8 +49,8 @@ struct dc_state {
   // workspace carve-up
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  void *vt, *tvn0, *vns, *kc, *tw0, *tw1, *d2, *zeta, *vv;
-  double *wstar, *cp, *dp, *drx, *dxx, *wtmp, *fe, *tau, *diag_part, *diag_out;
+  void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
+  double *wstar, *wtmp, *fe, *tau, *diag_part, *diag_out;
 };
 
 namespace {
@@ -72,7 +72,7 @@ dc_status fail(dc_status code, const std::string& msg) {
 size_t elem_size(dc_precision prec) { return prec == DC_PREC_MIXED ? sizeof(float) : sizeof(double); }
 
 struct Layout {
-  size_t vt, tvn0, vns, kc, tw0, tw1, d2, zeta, vv, wstar, cp, dp, drx, dxx, wtmp, fe, tau, dpart, dout, total;
+  size_t vt, tvn0, vns, kc, d2, zeta, vv, wstar, wtmp, fe, tau, dpart, dout, total;
 };
 
 Layout workspace_layout(const HostGrid& h, dc_precision prec) {
@@ -89,16 +89,10 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec) {
   L.tvn0 = take(K * h.es * r);
   L.vns = take(K * h.es * r);
   L.kc = take(K * h.cs * r);
-  L.tw0 = take(K1 * h.cs * r);
-  L.tw1 = take(K1 * h.cs * r);
   L.d2 = take(K1 * h.cs * r);
   L.zeta = take(K * h.vs * r);
   L.vv = take(3 * K * h.vs * r);
   L.wstar = take(K1 * h.cs * 8);
-  L.cp = take(K1 * h.cs * 8);
-  L.dp = take(K1 * h.cs * 8);
-  L.drx = take(K1 * h.cs * 8);
-  L.dxx = take(K1 * h.cs * 8);
   L.wtmp = take(K1 * h.cs * 8);
   L.fe = take(h.es * 8);
   L.tau = take(K1 * 8);
@@ -197,11 +191,8 @@ void default_tiles(const HostGrid& h, Tile* t) {
     int kb = (int)((long long)levels * nbx / 2048);
     return std::max(1, std::min(kb, 16));
   };
-  t[T_CURL] = {256, kb_for(h.nv, h.K)};
-  t[T_VT] = {256, kb_for(h.ne, h.K)};
-  t[T_CELLADV] = {256, kb_for(h.nc, h.K + 1)};
+  t[T_VC] = {256, kb_for(h.nc + h.nv, h.K)};
   t[T_EDGE] = {256, kb_for(h.ne, h.K)};
-  t[T_COL] = {64, 1};
   t[T_DVERT] = {256, kb_for(h.nv, h.K)};
   t[T_DCELL] = {256, kb_for(h.nc + h.nv, h.K + 1)};
   t[T_DEDGE] = {256, kb_for(h.ne, h.K)};
@@ -243,16 +234,10 @@ void enqueue_step(dc_state* s, double dt, int nsub) {
     b.tvn0 = static_cast<R*>(s->tvn0);
     b.vns = static_cast<R*>(s->vns);
     b.kc = static_cast<R*>(s->kc);
-    b.tw0 = static_cast<R*>(s->tw0);
-    b.tw1 = static_cast<R*>(s->tw1);
     b.d2 = static_cast<R*>(s->d2);
     b.zeta = static_cast<R*>(s->zeta);
     b.vv = static_cast<R*>(s->vv);
     b.ws = s->wstar;
-    b.cp = s->cp;
-    b.dp = s->dp;
-    b.drx = s->drx;
-    b.dxx = s->dxx;
     b.wtmp = s->wtmp;
     b.vn_out = static_cast<R*>(nxt.vn);
     b.w_out = (last && diffuse) ? s->wtmp : static_cast<double*>(nxt.w);
@@ -442,16 +427,10 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->tvn0 = w + L.tvn0;
   s->vns = w + L.vns;
   s->kc = w + L.kc;
-  s->tw0 = w + L.tw0;
-  s->tw1 = w + L.tw1;
   s->d2 = w + L.d2;
   s->zeta = w + L.zeta;
   s->vv = w + L.vv;
   s->wstar = reinterpret_cast<double*>(w + L.wstar);
-  s->cp = reinterpret_cast<double*>(w + L.cp);
-  s->dp = reinterpret_cast<double*>(w + L.dp);
-  s->drx = reinterpret_cast<double*>(w + L.drx);
-  s->dxx = reinterpret_cast<double*>(w + L.dxx);
   s->wtmp = reinterpret_cast<double*>(w + L.wtmp);
   s->fe = reinterpret_cast<double*>(w + L.fe);
   s->tau = reinterpret_cast<double*>(w + L.tau);

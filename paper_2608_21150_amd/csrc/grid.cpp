@@ -111,7 +111,8 @@ int build_host_grid(const dc_grid_desc* D, HostGrid* g, std::string* err) {
   if (!D) return fail(DC_EINVAL, "grid description is NULL");
   const int nc = D->n_cells, ne = D->n_edges, nv = D->n_verts, K = D->n_lev;
   if (nc <= 0 || ne <= 0 || nv <= 0 || K < 1) return fail(DC_EINVAL, "entity counts must be > 0 and n_lev >= 1");
-  if (nc > (1 << 28) || ne > (1 << 28) || nv > (1 << 28) || K > 4096) return fail(DC_EINVAL, "grid too large");
+  if (nc > (1 << 28) || ne > (1 << 28) || nv > (1 << 28)) return fail(DC_EINVAL, "grid too large");
+  if (K > 129) return fail(DC_EINVAL, "n_lev must be <= 129 (8 column chunks of at most 16 levels)");
   if (!D->e2c || !D->c2e || !D->e2v || !D->c2e2c || !D->vert_xyz || !D->cell_xyz || !D->edge_xyz ||
       !D->edge_length || !D->dual_edge_length || !D->cell_area || !D->dual_area || !D->edge_normal_xyz ||
       !D->z_half || !D->exner_ref_full || !D->theta_ref_full || !D->theta_ref_half || !D->dexner_dz_ref_half)

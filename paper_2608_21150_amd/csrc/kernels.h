@@ -9,8 +9,8 @@ namespace dc {
 
 // Kernel identifiers for per-launch timing.
 enum KernelId {
-  K_CURL_P = 0, K_VT_P, K_CELL_P, K_EDGE_P, K_COL_P,
-  K_CURL_C, K_VT_C, K_CELL_C, K_EDGE_C, K_COL_C,
+  K_VC_P = 0, K_EDGE_P, K_COL_P,
+  K_VC_C, K_EDGE_C, K_COL_C,
   K_DVERT, K_DDIV, K_DEDGE1, K_DCV2, K_DEDGE2,
   K_COUNT
 };
@@ -84,8 +84,8 @@ struct Bufs {
   const R* vn;
   const double *w, *rho, *ex, *th;
   // workspace
-  R *vt, *tvn0, *vns, *kc, *tw0, *tw1, *d2, *zeta, *vv;
-  double *ws, *cp, *dp, *drx, *dxx, *wtmp;
+  R *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
+  double *ws, *wtmp;
   // outputs of the corrector
   R* vn_out;
   double *w_out, *rho_out, *ex_out, *th_out;
@@ -102,8 +102,10 @@ template <typename R>
 void launch_diag(const DevGrid& g, const R* vn, const double* w, const double* rho, const double* th,
                  const double* ex, double* partial, double* out, hipStream_t s);
 int diag_partial_count(const DevGrid& g);
+// chunks (waves) per 64-column block of the column kernel; *lm = rows per chunk
+int col_chunks(int K, int* lm);
 
 // indices into the tile table
-enum TileId { T_CURL = 0, T_VT, T_CELLADV, T_EDGE, T_COL, T_DVERT, T_DCELL, T_DEDGE, T_COUNT };
+enum TileId { T_VC = 0, T_EDGE, T_DVERT, T_DCELL, T_DEDGE, T_COUNT };
 
 }  // namespace dc

@@ -13,6 +13,8 @@
 // column solver, w/rho/exner/theta_v and flux-divergence sums are always
 // FP64.  No floating-point atomics: results do not depend on scheduling.
 
+#include <algorithm>
+
 #include "internal.h"
 #include "kernels.h"
 
@@ -33,79 +35,72 @@ __device__ __forceinline__ void tile_coords(int& bx, int& by) {
 __device__ __forceinline__ const double* vt_row(const DevGrid& g, int tab) { return g.vert + (size_t)tab * (g.K + 1); }
 
 // ---------------------------------------------------------------------------
-// vertex: relative vorticity zeta_v = (1/A_v) sum sig d_e vn_e
+// Tangential wind at edge e by Perot reconstruction: a 5-point stencil over
+// the edge and its four e2c2e neighbours (weights precomputed on the host).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(256) k_curl(DevGrid g, const R* __restrict__ vn, R* __restrict__ zeta, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int v = bx * blockDim.x + threadIdx.x;
-  if (v >= g.nv) return;
-  int idx[6];
-  R cf[6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    idx[s] = g.v2e[s * g.vs + v];
-    cf[s] = (R)g.kcurl[s * g.vs + v];
-  }
-  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-  for (int k = k0; k < k1; ++k) {
-    const R* row = vn + (size_t)k * g.es;
-    R acc = cf[0] * row[idx[0]];
-#pragma unroll
-    for (int s = 1; s < 6; ++s) acc += cf[s] * row[idx[s]];
-    zeta[(size_t)k * g.vs + v] = acc;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// edge: tangential wind by Perot reconstruction (weights precomputed)
-// ---------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(256) k_vt(DevGrid g, const R* __restrict__ vn, R* __restrict__ vt, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int e = bx * blockDim.x + threadIdx.x;
-  if (e >= g.ne) return;
+struct VtStencil {
   int idx[4];
-  R cf[5];
-  cf[0] = (R)g.kvt[e];
+  R w[5];
+  __device__ __forceinline__ void load(const DevGrid& g, int e) {
+    w[0] = (R)g.kvt[e];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    idx[s] = g.e2c2e[s * g.es + e];
-    cf[1 + s] = (R)g.kvt[(1 + s) * g.es + e];
+    for (int s = 0; s < 4; ++s) {
+      idx[s] = g.e2c2e[s * g.es + e];
+      w[1 + s] = (R)g.kvt[(1 + s) * g.es + e];
+    }
   }
-  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-  for (int k = k0; k < k1; ++k) {
-    const R* row = vn + (size_t)k * g.es;
-    R acc = cf[0] * row[e];
+  __device__ __forceinline__ R apply(const R* __restrict__ row, int e) const {
+    R acc = w[0] * row[e];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc += cf[1 + s] * row[idx[s]];
-    vt[(size_t)k * g.es + e] = acc;
+    for (int s = 0; s < 4; ++s) acc += w[1 + s] * row[idx[s]];
+    return acc;
   }
-}
+};
 
 // ---------------------------------------------------------------------------
-// cell: kinetic energy K_c, vertical-wind advection T_w (half levels) and,
-// in the corrector, the divergence-damping field D2 = laps(div vn).
-// Grid y covers the K+1 half levels.
+// vertex + cell pass (one launch, blocks [0, ncb) are cells):
+//  vertices: relative vorticity zeta_v = (1/A_v) sum sig d_e vn_e
+//  cells:    kinetic energy K_c = mean over the 3 edges of (vn^2 + vt^2)/2,
+//            vt reconstructed in place; in the corrector also the
+//            divergence-damping field D2 = laps(div vn).
 // ---------------------------------------------------------------------------
 template <typename R, bool CORR>
-__global__ void __launch_bounds__(256) k_cell_adv(DevGrid g, const R* __restrict__ vn, const R* __restrict__ vt,
-                                                  const double* __restrict__ w, R* __restrict__ kc,
-                                                  R* __restrict__ tw, R* __restrict__ d2, int kb) {
+__global__ void __launch_bounds__(256) k_vc(DevGrid g, const R* __restrict__ vn, R* __restrict__ zeta,
+                                            R* __restrict__ kc, R* __restrict__ d2, int ncb, int kb) {
   int bx, by;
   tile_coords(bx, by);
+  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
+  if (bx >= ncb) {
+    const int v = (bx - ncb) * blockDim.x + threadIdx.x;
+    if (v >= g.nv) return;
+    int idx[6];
+    R cf[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      idx[s] = g.v2e[s * g.vs + v];
+      cf[s] = (R)g.kcurl[s * g.vs + v];
+    }
+    for (int k = k0; k < k1; ++k) {
+      const R* row = vn + (size_t)k * g.es;
+      R acc = cf[0] * row[idx[0]];
+#pragma unroll
+      for (int s = 1; s < 6; ++s) acc += cf[s] * row[idx[s]];
+      zeta[(size_t)k * g.vs + v] = acc;
+    }
+    return;
+  }
   const int c = bx * blockDim.x + threadIdx.x;
   if (c >= g.nc) return;
-  const int K = g.K;
   int ie[3], nb[3];
   R kd[3];
+  VtStencil<R> vts[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     ie[i] = g.c2e[i * g.cs + c];
     nb[i] = g.c2e2c[i * g.cs + c];
     kd[i] = (R)g.kdiv[i * g.cs + c];
+    vts[i].load(g, ie[i]);
   }
   int ie2[3][3];
   R kd2[3][3], kl[3];
@@ -120,46 +115,25 @@ __global__ void __launch_bounds__(256) k_cell_adv(DevGrid g, const R* __restrict
       }
     }
   }
-  const double* idzc2 = vt_row(g, VT_IDZC2);
-  const int k0 = by * kb, k1 = min(K + 1, k0 + kb);
   for (int k = k0; k < k1; ++k) {
-    if (k < K) {
-      const R* vrow = vn + (size_t)k * g.es;
-      const R* trow = vt + (size_t)k * g.es;
-      R ke = R(0);
+    const R* vrow = vn + (size_t)k * g.es;
+    R ke = R(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const R a = vrow[ie[i]], b = vts[i].apply(vrow, ie[i]);
+      ke += R(0.5) * (a * a + b * b);
+    }
+    kc[(size_t)k * g.cs + c] = ke / R(3);
+    if (CORR) {
+      const R dc = kd[0] * vrow[ie[0]] + kd[1] * vrow[ie[1]] + kd[2] * vrow[ie[2]];
+      R acc = R(0);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const R a = vrow[ie[i]], b = trow[ie[i]];
-        ke += R(0.5) * (a * a + b * b);
+        const R dn = kd2[i][0] * vrow[ie2[i][0]] + kd2[i][1] * vrow[ie2[i][1]] + kd2[i][2] * vrow[ie2[i][2]];
+        acc += kl[i] * (dn - dc);
       }
-      kc[(size_t)k * g.cs + c] = ke / R(3);
-      if (CORR) {
-        R dc = kd[0] * vrow[ie[0]] + kd[1] * vrow[ie[1]] + kd[2] * vrow[ie[2]];
-        R acc = R(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const R dn = kd2[i][0] * vrow[ie2[i][0]] + kd2[i][1] * vrow[ie2[i][1]] + kd2[i][2] * vrow[ie2[i][2]];
-          acc += kl[i] * (dn - dc);
-        }
-        d2[(size_t)k * g.cs + c] = acc;
-      }
+      d2[(size_t)k * g.cs + c] = acc;
     }
-    R t = R(0);
-    if (k >= 1 && k <= K - 1) {
-      const R* va = vn + (size_t)(k - 1) * g.es;
-      const R* vb = vn + (size_t)k * g.es;
-      const double* wr = w + (size_t)k * g.cs;
-      const double wc = wr[c];
-      R h = R(0);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const R vie = R(0.5) * (va[ie[i]] + vb[ie[i]]);
-        h += kd[i] * vie * (R)(wr[nb[i]] - wc);
-      }
-      const double dwdz = (w[(size_t)(k - 1) * g.cs + c] - w[(size_t)(k + 1) * g.cs + c]) * idzc2[k];
-      t = R(-0.5) * h - (R)(wc * dwdz);
-    }
-    tw[(size_t)k * g.cs + c] = t;
   }
 }
 
@@ -172,8 +146,7 @@ __global__ void __launch_bounds__(256) k_cell_adv(DevGrid g, const R* __restrict
 // substep in both passes.
 // ---------------------------------------------------------------------------
 template <typename R, bool CORR>
-__global__ void __launch_bounds__(256) k_edge(DevGrid g, const R* __restrict__ vn, const R* __restrict__ vt,
-                                              const R* __restrict__ zeta, const R* __restrict__ kc,
+__global__ void __launch_bounds__(256) k_edge(DevGrid g, const R* __restrict__ vn, const R* __restrict__ zeta, const R* __restrict__ kc,
                                               const double* __restrict__ w, const double* __restrict__ ex,
                                               const double* __restrict__ th, R* __restrict__ tvn0,
                                               R* __restrict__ vout, const R* __restrict__ vn_now,
@@ -188,6 +161,8 @@ __global__ void __launch_bounds__(256) k_edge(DevGrid g, const R* __restrict__ v
   const double invd = g.invd[e];
   const R invd_r = (R)invd;
   const R fe = (R)g.fe[e];
+  VtStencil<R> vts;
+  vts.load(g, e);
   const double* idzf = vt_row(g, VT_IDZF);
   const double* exref = vt_row(g, VT_EXREF);
   const int k0 = by * kb, k1 = min(K, k0 + kb);
@@ -205,7 +180,8 @@ __global__ void __launch_bounds__(256) k_edge(DevGrid g, const R* __restrict__ v
     const double* wa = w + (size_t)j * g.cs;
     const double* wb = wa + g.cs;
     const R wef = (R)(0.5 * (0.5 * (wa[c0] + wa[c1]) + 0.5 * (wb[c0] + wb[c1])));
-    const R tvn = (ze + fe) * vt[re] - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
+    const R vt = vts.apply(vn + (size_t)j * g.es, e);
+    const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
     const size_t rc = (size_t)j * g.cs;
     const double exr = exref[j];
     const R gex = (R)((ex[rc + c1] - exr) - (ex[rc + c0] - exr)) * invd_r;
@@ -222,183 +198,324 @@ __global__ void __launch_bounds__(256) k_edge(DevGrid g, const R* __restrict__ v
 }
 
 // ---------------------------------------------------------------------------
-// column: flux divergences, explicit parts, tridiagonal w solve (Thomas,
-// no pivoting: every pivot is >= 1 for this matrix), sponge, and in the
-// corrector the increment updates of rho, exner, theta_v.  One thread owns
-// one column and sweeps it top to bottom and back; the elimination factors
-// are kept in a [K+1][cs] scratch (coalesced rows).
+// column: vertical-wind advection T_w, flux divergences, explicit parts, the
+// tridiagonal w solve, sponge and (corrector) the increment updates of rho,
+// exner and theta_v.
+// Layout: a block holds 64 neighbouring columns (one per lane, so every
+// level row is one coalesced 512-byte access) and P waves; wave p owns a
+// chunk of at most LM consecutive half levels (rows) of those columns.
+// Solve: partition method.  Each wave eliminates its chunk in registers
+// (down sweep, then up sweep), leaving every row expressed through the last
+// row of the chunk above and the first row of the chunk below; the interface
+// unknowns form a 2x2-block tridiagonal system of P-1 blocks that wave 0
+// solves through LDS; every wave then back-substitutes its rows.  The matrix
+// is diagonally similar to I + symmetric positive semi-definite, so no
+// pivoting is needed anywhere.  No HBM scratch.  Rows 0 and K are the w = 0
+// boundaries.
 // ---------------------------------------------------------------------------
-template <typename R, bool CORR>
-__global__ void __launch_bounds__(64) k_col(DevGrid g, const double* __restrict__ w, const double* __restrict__ rho,
-                                            const double* __restrict__ ex, const double* __restrict__ th,
-                                            const R* __restrict__ vnf, const R* __restrict__ tw0,
-                                            const R* __restrict__ tw1, double* __restrict__ w_out,
-                                            double* __restrict__ rho_out, double* __restrict__ ex_out,
-                                            double* __restrict__ th_out, double* __restrict__ cpv,
-                                            double* __restrict__ dpv, double* __restrict__ drxv,
-                                            double* __restrict__ dxxv, StepCoef cf) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.nc) return;
-  const int K = g.K, cs = g.cs;
-  int ie[3], nb[3];
-  double kd[3];
+template <typename R>
+struct ColArgs {
+  const double *w, *rho, *ex, *th;  // state at the start of the substep
+  const R* vn;                       // vn at the start of the substep (T_w)
+  const R* vnf;                      // vn of the mass fluxes (vn* / new vn)
+  const R* vns;                      // corrector: predicted vn* (T_w*)
+  const double* ws;                  // corrector: predicted w* (T_w*)
+  double *w_out, *rho_out, *ex_out, *th_out;
+};
+
+// T_w at half level k (1 <= k <= K-1) of column c from vn and w (w_up, w_k,
+// w_dn: the column's own w at half levels k-1, k, k+1).
+template <typename R>
+__device__ __forceinline__ double col_tw(const DevGrid& g, const R* __restrict__ vn, const double* __restrict__ w,
+                                         double w_up, double w_k, double w_dn, int k, const int* ie, const int* nb,
+                                         const R* kd) {
+  const R* va = vn + (size_t)(k - 1) * g.es;
+  const R* vb = vn + (size_t)k * g.es;
+  const double* wr = w + (size_t)k * g.cs;
+  R hs = R(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    ie[i] = g.c2e[i * cs + c];
-    nb[i] = g.c2e2c[i * cs + c];
-    kd[i] = g.kdiv[i * cs + c];
+    const R vie = R(0.5) * (va[ie[i]] + vb[ie[i]]);
+    hs += kd[i] * vie * (R)(wr[nb[i]] - w_k);
   }
-  const double* idzf = vt_row(g, VT_IDZF);
-  const double* idzh = vt_row(g, VT_IDZH);
-  const double* exref = vt_row(g, VT_EXREF);
-  const double* thref = vt_row(g, VT_THREF);
-  const double* thric = vt_row(g, VT_THREFIC);
-  const double* dxric = vt_row(g, VT_DEXREFIC);
-  const double eta = cf.eta, dtau = cf.dtau, cpd = cf.cpd;
-  const double oneme = 1.0 - eta;
+  const double dwdz = (w_up - w_dn) * vt_row(g, VT_IDZC2)[k];
+  return (double)(R(-0.5) * hs - (R)(w_k * dwdz));
+}
 
-  // sliding window: full levels j (cur) and j+1 (nxt); half levels j and j+1
-  double rho_c = rho[c], th_c = th[c], ex_c = ex[c];
-  double thp_c = th_c - thref[0], exp_c = ex_c - exref[0];
-  double ric_c = rho_c, atil_c = 0.0;  // half level 0
-  double gam_c = 0.0, zth_c = 0.0;     // half level 0 (unused)
-  double w_c = w[c];
-  double beta_p = 0.0, e_p = 0.0, aeta_p = 0.0;  // full level j-1 / half level j-1
-  double cp_p = 0.0, dp_p = 0.0;
-  for (int j = 0; j < K; ++j) {
-    // half level j+1
-    double rho_n = 0.0, th_n = 0.0, ex_n = 0.0, thp_n = 0.0, exp_n = 0.0;
-    double ric_n, atil_n, gam_n = 0.0, zth_n = 0.0;
-    if (j + 1 < K) {
-      const size_t r = (size_t)(j + 1) * cs + c;
-      rho_n = rho[r];
-      th_n = th[r];
-      ex_n = ex[r];
-      thp_n = th_n - thref[j + 1];
-      exp_n = ex_n - exref[j + 1];
-      ric_n = 0.5 * (rho_c + rho_n);
-      const double thp_ic = 0.5 * (thp_c + thp_n);
-      const double th_ic = thric[j + 1] + thp_ic;
-      atil_n = th_ic * ric_n;
-      gam_n = dtau * cpd * eta * th_ic * idzh[j + 1];
-      zth_n = oneme * th_ic * (exp_c - exp_n) * idzh[j + 1] + thp_ic * dxric[j + 1];
-    } else {
-      ric_n = rho_c;
-      atil_n = 0.0;
-    }
-    const double w_n = w[(size_t)(j + 1) * cs + c];
-    // flux divergences at full level j
-    const R* vr = vnf + (size_t)j * g.es;
-    const double* rr = rho + (size_t)j * cs;
-    const double* tr = th + (size_t)j * cs;
-    double dm = 0.0, dth = 0.0;
+// State of one level of a column: full level j and half level j.
+struct ColLev {
+  double rho, th, ex, thp, exp_;  // full level j
+  double w, ws;                    // w, w* at half level j
+  double ric, atil, gam, zth;      // half level j
+};
+
+__device__ __forceinline__ void col_load(const DevGrid& g, const double* __restrict__ rho,
+                                         const double* __restrict__ th, const double* __restrict__ ex, int j, int c,
+                                         ColLev& L) {
+  const size_t r = (size_t)j * g.cs + c;
+  L.rho = rho[r];
+  L.th = th[r];
+  L.ex = ex[r];
+  L.thp = L.th - vt_row(g, VT_THREF)[j];
+  L.exp_ = L.ex - vt_row(g, VT_EXREF)[j];
+}
+
+// half-level quantities of level b (= j1) from full levels j1-1 (a) and j1 (b)
+__device__ __forceinline__ void col_half(const DevGrid& g, const ColLev& a, ColLev& b, int j1, double dtau,
+                                         double cpd, double eta) {
+  b.ric = 0.5 * (a.rho + b.rho);
+  const double thp_ic = 0.5 * (a.thp + b.thp);
+  const double th_ic = vt_row(g, VT_THREFIC)[j1] + thp_ic;
+  b.atil = th_ic * b.ric;
+  const double idzh = vt_row(g, VT_IDZH)[j1];
+  b.gam = dtau * cpd * eta * th_ic * idzh;
+  b.zth = (1.0 - eta) * th_ic * (a.exp_ - b.exp_) * idzh + thp_ic * vt_row(g, VT_DEXREFIC)[j1];
+}
+
+template <typename R, bool CORR, int LM>
+__global__ void __launch_bounds__(512) k_colq(DevGrid g, ColArgs<R> a, StepCoef cf, int P) {
+  extern __shared__ double s_red[];  // [6][P][64]
+  const int K = g.K, cs = g.cs;
+  const int cl = threadIdx.x & 63, p = threadIdx.x >> 6;
+  int bx, by;
+  tile_coords(bx, by);
+  const int c0 = bx * 64 + cl;
+  const bool ok = c0 < g.nc;
+  const int c = ok ? c0 : 0;  // padding lanes compute column 0 and store nothing
+  // rows (half levels 1..K-1) of this chunk: [s, s + n)
+  const int nrow = K - 1;
+  const int base = nrow / P, extra = nrow - base * P;
+  const int n = base + (p < extra ? 1 : 0);
+  const int s = 1 + p * base + min(p, extra);
+  const int h = s - 1;  // full level above the first row (halo; chunk 0 owns it)
+  const double* idzf = vt_row(g, VT_IDZF);
+  const double eta = cf.eta, dtau = cf.dtau, cpd = cf.cpd, oneme = 1.0 - eta;
+  int ie[3], nb[3];
+  double kd[3];
+  R kdr[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const R rho_e = (R)(0.5 * (rho_c + rr[nb[i]]));
-      const R th_e = (R)(0.5 * (th_c + tr[nb[i]]));
-      const R fm = rho_e * vr[ie[i]];
-      const R ft = fm * th_e;
-      dm += kd[i] * (double)fm;
-      dth += kd[i] * (double)ft;
-    }
-    const double b = dtau * cf.rd_cvd * ex_c / (rho_c * th_c);
-    const double beta = b * idzf[j];
-    const double drx = -dtau * (dm + oneme * (ric_c * w_c - ric_n * w_n) * idzf[j]);
-    const double dxx = -b * (dth + oneme * (atil_c * w_c - atil_n * w_n) * idzf[j]);
-    const double e_c = exp_c + dxx;
-    if (CORR) {
-      drxv[(size_t)j * cs + c] = drx;
-      dxxv[(size_t)j * cs + c] = dxx;
-    }
-    const double aeta_c = eta * atil_c, aeta_n = eta * atil_n;
-    if (j >= 1) {
-      // row of half level j
-      double tw = (double)tw0[(size_t)j * cs + c];
-      if (CORR) tw = cf.a0 * tw + cf.a1 * (double)tw1[(size_t)j * cs + c];
-      const double wx = w_c + dtau * (tw - cpd * zth_c);
-      const double A = -gam_c * beta_p * aeta_p;
-      const double B = 1.0 + gam_c * aeta_c * (beta_p + beta);
-      const double C = -gam_c * beta * aeta_n;
-      const double rhs = wx - gam_c * (e_p - e_c);
-      const double den = B - A * cp_p;
-      const double cpk = C / den;
-      const double dpk = (rhs - A * dp_p) / den;
-      cpv[(size_t)j * cs + c] = cpk;
-      dpv[(size_t)j * cs + c] = dpk;
-      cp_p = cpk;
-      dp_p = dpk;
-    }
-    // shift the window
-    beta_p = beta;
-    e_p = e_c;
-    aeta_p = aeta_c;
-    rho_c = rho_n;
-    th_c = th_n;
-    ex_c = ex_n;
-    thp_c = thp_n;
-    exp_c = exp_n;
-    ric_c = ric_n;
-    atil_c = atil_n;
-    gam_c = gam_n;
-    zth_c = zth_n;
-    w_c = w_n;
+  for (int q = 0; q < 3; ++q) {
+    ie[q] = g.c2e[q * cs + c];
+    nb[q] = g.c2e2c[q * cs + c];
+    kd[q] = g.kdiv[q * cs + c];
+    kdr[q] = (R)kd[q];
   }
-  // back substitution, sponge; corrector: increment updates level by level
-  const double* tau = g.tau;
-  w_out[(size_t)K * cs + c] = 0.0;
-  double x_n = 0.0;    // undamped solution at half level k+1
-  double ws_n = 0.0;   // damped w at half level k+1
-  // window for the corrector updates (full level k and half levels k, k+1)
-  double rho_k = 0.0, th_k = 0.0, ex_k = 0.0, thp_k = 0.0;
-  double ric_kn = 0.0, atil_kn = 0.0;  // half level k+1
-  if (CORR) {
-    const size_t r = (size_t)(K - 1) * cs + c;
-    rho_k = rho[r];
-    th_k = th[r];
-    ex_k = ex[r];
-    thp_k = th_k - thref[K - 1];
-    ric_kn = rho_k;
-    atil_kn = 0.0;
+
+  // ---- forward sweep over levels h..h+n: explicit parts, rows, down sweep ----
+  double cpv[LM], dpv[LM], lpv[LM];
+  double drxv[LM + 1], dxxv[LM + 1];
+  ColLev cur;
+  col_load(g, a.rho, a.th, a.ex, h, c, cur);
+  cur.w = a.w[(size_t)h * cs + c];
+  cur.ws = CORR ? a.ws[(size_t)h * cs + c] : 0.0;
+  double w_up = 0.0, ws_up = 0.0;
+  if (h >= 1) {
+    ColLev up;
+    col_load(g, a.rho, a.th, a.ex, h - 1, c, up);
+    col_half(g, up, cur, h, dtau, cpd, eta);
+    w_up = a.w[(size_t)(h - 1) * cs + c];
+    if (CORR) ws_up = a.ws[(size_t)(h - 1) * cs + c];
+  } else {
+    cur.ric = cur.rho;
+    cur.atil = 0.0;
+    cur.gam = 0.0;
+    cur.zth = 0.0;
   }
-  for (int k = K - 1; k >= 0; --k) {
-    double ws_k = 0.0;
-    if (k >= 1) {
-      const double x = dpv[(size_t)k * cs + c] - cpv[(size_t)k * cs + c] * x_n;
-      x_n = x;
-      ws_k = x / (1.0 + dtau * tau[k]);
-    }
-    w_out[(size_t)k * cs + c] = ws_k;
-    if (CORR) {
-      // half level k quantities need full level k-1
-      double rho_m = 0.0, th_m = 0.0, thp_m = 0.0, ric_k, atil_k;
-      if (k >= 1) {
-        const size_t r = (size_t)(k - 1) * cs + c;
-        rho_m = rho[r];
-        th_m = th[r];
-        thp_m = th_m - thref[k - 1];
-        ric_k = 0.5 * (rho_m + rho_k);
-        atil_k = (thric[k] + 0.5 * (thp_m + thp_k)) * ric_k;
+  double beta_p = 0.0, e_p = 0.0, atil_p = 0.0;
+#pragma unroll
+  for (int i = 0; i <= LM; ++i) {
+    if (i <= n) {
+      const int j = h + i;
+      ColLev nx;
+      if (j + 1 < K) {
+        col_load(g, a.rho, a.th, a.ex, j + 1, c, nx);
+        col_half(g, cur, nx, j + 1, dtau, cpd, eta);
+        nx.w = a.w[(size_t)(j + 1) * cs + c];
+        nx.ws = CORR ? a.ws[(size_t)(j + 1) * cs + c] : 0.0;
       } else {
-        ric_k = rho_k;
-        atil_k = 0.0;
+        nx.ric = cur.rho;
+        nx.atil = 0.0;
+        nx.w = a.w[(size_t)K * cs + c];
+        nx.ws = 0.0;
       }
-      const size_t r = (size_t)k * cs + c;
-      const double b = dtau * cf.rd_cvd * ex_k / (rho_k * th_k);
-      const double beta = b * idzf[k];
-      const double drho = drxv[r] - dtau * eta * (ric_k * ws_k - ric_kn * ws_n) * idzf[k];
-      const double dex = dxxv[r] - beta * (eta * atil_k * ws_k - eta * atil_kn * ws_n);
-      const double rho_new = rho_k + drho;
-      rho_out[r] = rho_new;
-      ex_out[r] = ex_k + dex;
-      th_out[r] = th_k + (rho_k * th_k * cf.cvd_rd * dex / ex_k - th_k * drho) / rho_new;
-      rho_k = rho_m;
-      th_k = th_m;
-      thp_k = thp_m;
-      if (k >= 1) ex_k = ex[(size_t)(k - 1) * cs + c];
-      ric_kn = ric_k;
-      atil_kn = atil_k;
+      // mass and theta fluxes, explicit parts at full level j
+      double dm = 0.0, dth = 0.0;
+      {
+        const R* vr = a.vnf + (size_t)j * g.es;
+        const double* rr = a.rho + (size_t)j * cs;
+        const double* tr = a.th + (size_t)j * cs;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const R rho_e = (R)(0.5 * (cur.rho + rr[nb[q]]));
+          const R th_e = (R)(0.5 * (cur.th + tr[nb[q]]));
+          const R fm = rho_e * vr[ie[q]];
+          const R ft = fm * th_e;
+          dm += kd[q] * (double)fm;
+          dth += kd[q] * (double)ft;
+        }
+      }
+      const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
+      const double beta = b * idzf[j];
+      const double drx = -dtau * (dm + oneme * (cur.ric * cur.w - nx.ric * nx.w) * idzf[j]);
+      const double dxx = -b * (dth + oneme * (cur.atil * cur.w - nx.atil * nx.w) * idzf[j]);
+      const double e_c = cur.exp_ + dxx;
+      drxv[i] = drx;
+      dxxv[i] = dxx;
+      if (i >= 1) {
+        // row of half level j, then one step of the down sweep
+        double tw = col_tw<R>(g, a.vn, a.w, w_up, cur.w, nx.w, j, ie, nb, kdr);
+        if (CORR) tw = cf.a0 * tw + cf.a1 * col_tw<R>(g, a.vns, a.ws, ws_up, cur.ws, nx.ws, j, ie, nb, kdr);
+        const double wx = cur.w + dtau * (tw - cpd * cur.zth);
+        const double A = -cur.gam * beta_p * (eta * atil_p);
+        const double B = 1.0 + cur.gam * (eta * cur.atil) * (beta_p + beta);
+        const double C = -cur.gam * beta * (eta * nx.atil);
+        const double rhs = wx - cur.gam * (e_p - e_c);
+        if (i == 1) {
+          cpv[0] = C / B;
+          dpv[0] = rhs / B;
+          lpv[0] = A / B;
+        } else {
+          const double den = B - A * cpv[i - 2];
+          cpv[i - 1] = C / den;
+          dpv[i - 1] = (rhs - A * dpv[i - 2]) / den;
+          lpv[i - 1] = -A * lpv[i - 2] / den;
+        }
+      }
+      beta_p = beta;
+      e_p = e_c;
+      atil_p = cur.atil;
+      w_up = cur.w;
+      ws_up = cur.ws;
+      cur = nx;
     }
-    ws_n = ws_k;
+  }
+  // ---- up sweep: row i of the chunk = d_i - u_i x_below - v_i x_above ----
+#pragma unroll
+  for (int i = LM - 2; i >= 0; --i) {
+    if (i < n - 1) {
+      dpv[i] = dpv[i] - cpv[i] * dpv[i + 1];
+      lpv[i] = lpv[i] - cpv[i] * lpv[i + 1];
+      cpv[i] = -cpv[i] * cpv[i + 1];
+    }
+  }
+  // ---- interface system (2x2 blocks), solved by wave 0 ----
+  const int sP = P * 64;
+  double xa = 0.0, xb = 0.0;  // x in the last row of the chunk above, first row of the chunk below
+  if (P > 1) {
+    double dl = 0.0, ul = 0.0, vl = 0.0;
+#pragma unroll
+    for (int i = 0; i < LM; ++i)
+      if (i == n - 1) {
+        dl = dpv[i];
+        ul = cpv[i];
+        vl = lpv[i];
+      }
+    const int o = p * 64 + cl;
+    s_red[0 * sP + o] = dl;
+    s_red[1 * sP + o] = ul;
+    s_red[2 * sP + o] = vl;
+    s_red[3 * sP + o] = dpv[0];
+    s_red[4 * sP + o] = cpv[0];
+    s_red[5 * sP + o] = lpv[0];
+    __syncthreads();
+    if (p == 0) {
+      double c0p = 0.0, g0p = 0.0;
+      for (int q = 0; q < P - 1; ++q) {
+        const int oq = q * 64 + cl, on = (q + 1) * 64 + cl;
+        const double dz = s_red[0 * sP + oq], uz = s_red[1 * sP + oq], vz = s_red[2 * sP + oq];
+        const double df = s_red[3 * sP + on], uf = s_red[4 * sP + on], vf = s_red[5 * sP + on];
+        const double bq = uz - vz * c0p;
+        const double det = 1.0 - bq * vf;
+        const double r0 = dz - vz * g0p, r1 = df;
+        const double g0 = (r0 - bq * r1) / det, g1 = (r1 - vf * r0) / det;
+        const double k0 = -bq * uf / det, k1 = uf / det;
+        s_red[0 * sP + oq] = k0;
+        s_red[1 * sP + oq] = k1;
+        s_red[2 * sP + oq] = g0;
+        s_red[3 * sP + oq] = g1;
+        c0p = k0;
+        g0p = g0;
+      }
+      double fnext = 0.0;
+      for (int q = P - 2; q >= 0; --q) {
+        const int oq = q * 64 + cl;
+        const double y0 = s_red[2 * sP + oq] - s_red[0 * sP + oq] * fnext;
+        const double y1 = s_red[3 * sP + oq] - s_red[1 * sP + oq] * fnext;
+        s_red[4 * sP + oq] = y0;  // last row of chunk q
+        s_red[5 * sP + oq] = y1;  // first row of chunk q + 1
+        fnext = y1;
+      }
+    }
+    __syncthreads();
+    if (p > 0) xa = s_red[4 * sP + (p - 1) * 64 + cl];
+    if (p < P - 1) xb = s_red[5 * sP + p * 64 + cl];
+  }
+  // ---- back substitution and sponge: w* at half levels s..s+n-1 ----
+  // (row i of the chunk is half level s + i; w*(h) of the chunk above is
+  // needed only by chunk 0, where it is the w = 0 boundary)
+  const int e = s + n;
+  const double w_below = (e < K) ? xb / (1.0 + dtau * g.tau[e]) : 0.0;
+  if (!CORR) {
+#pragma unroll
+    for (int i = 0; i < LM; ++i) {
+      if (i < n && ok) {
+        const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
+        a.w_out[(size_t)(s + i) * cs + c] = x / (1.0 + dtau * g.tau[s + i]);
+      }
+    }
+  }
+  if (ok && p == 0) a.w_out[c] = 0.0;
+  if (ok && p == P - 1) a.w_out[(size_t)K * cs + c] = 0.0;
+
+  // ---- corrector: w*, and increment updates of rho, exner, theta_v at
+  // full levels h..h+n (level h only in chunk 0) ----
+  if (CORR) {
+    ColLev lv;
+    col_load(g, a.rho, a.th, a.ex, h, c, lv);
+    if (h >= 1) {
+      ColLev up;
+      col_load(g, a.rho, a.th, a.ex, h - 1, c, up);
+      col_half(g, up, lv, h, dtau, cpd, eta);
+    } else {
+      lv.ric = lv.rho;
+      lv.atil = 0.0;
+    }
+    double w0 = 0.0;  // w* at half level h (used by chunk 0 only: the top boundary)
+#pragma unroll
+    for (int i = 0; i <= LM; ++i) {
+      if (i <= n) {
+        const int j = h + i;
+        double w1 = w_below;
+        if (i < n) {
+          const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
+          w1 = x / (1.0 + dtau * g.tau[s + i]);
+          if (ok) a.w_out[(size_t)(s + i) * cs + c] = w1;
+        }
+        ColLev nx;
+        if (j + 1 < K) {
+          col_load(g, a.rho, a.th, a.ex, j + 1, c, nx);
+          col_half(g, lv, nx, j + 1, dtau, cpd, eta);
+        } else {
+          nx.ric = lv.rho;
+          nx.atil = 0.0;
+        }
+        if (i >= 1 || p == 0) {
+          const double b = dtau * cf.rd_cvd * lv.ex / (lv.rho * lv.th);
+          const double beta = b * idzf[j];
+          const double drho = drxv[i] - dtau * eta * (lv.ric * w0 - nx.ric * w1) * idzf[j];
+          const double dex = dxxv[i] - beta * (eta * lv.atil * w0 - eta * nx.atil * w1);
+          const double rho_new = lv.rho + drho;
+          if (ok) {
+            const size_t r = (size_t)j * cs + c;
+            a.rho_out[r] = rho_new;
+            a.ex_out[r] = lv.ex + dex;
+            a.th_out[r] = lv.th + (lv.rho * lv.th * cf.cvd_rd * dex / lv.ex - lv.th * drho) / rho_new;
+          }
+        }
+        w0 = w1;
+        lv = nx;
+      }
+    }
   }
 }
 
@@ -713,9 +830,32 @@ inline dim3 grid2(int n, int levels, const Tile& t) {
 
 }  // namespace
 
+// Column chunking: at most 8 waves (chunks) per block of 64 columns, chunk
+// length LM in {8, 12, 16} (the smallest that fits); chunks hold >= 2 rows
+// whenever there is more than one.  Supports n_lev <= 129.
+int col_chunks(int K, int* lm) {
+  const int nrow = std::max(K - 1, 0);
+  *lm = nrow <= 64 ? 8 : (nrow <= 96 ? 12 : 16);
+  return std::max(1, (nrow + *lm - 1) / *lm);
+}
+
+template <typename R, bool CORR>
+void launch_col(const DevGrid& g, const ColArgs<R>& a, const StepCoef& c, hipStream_t s) {
+  int lm;
+  const int P = col_chunks(g.K, &lm);
+  const int nblk = (g.nc + 63) / 64;
+  const size_t smem = P > 1 ? 6 * sizeof(double) * 64 * (size_t)P : 0;
+  if (lm == 8)
+    k_colq<R, CORR, 8><<<nblk, 64 * P, smem, s>>>(g, a, c, P);
+  else if (lm == 12)
+    k_colq<R, CORR, 12><<<nblk, 64 * P, smem, s>>>(g, a, c, P);
+  else
+    k_colq<R, CORR, 16><<<nblk, 64 * P, smem, s>>>(g, a, c, P);
+}
+
 const char* const kKernelNames[K_COUNT] = {
-    "curl_pred", "vt_pred", "cell_adv_pred", "edge_pred", "column_pred",
-    "curl_corr", "vt_corr", "cell_adv_corr", "edge_corr", "column_corr",
+    "vort_ke_pred", "edge_pred", "column_pred",
+    "vort_ke_corr", "edge_corr", "column_corr",
     "diff_vertex", "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2"};
 
 #define LAUNCH(id, ...)                     \
@@ -733,26 +873,20 @@ template <typename R>
 void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* T, hipStream_t s, Prof* prof) {
   const int K = g.K;
   // predictor: advective tendencies at the substep start, momentum, column
-  LAUNCH(K_CURL_P, k_curl<R><<<grid2(g.nv, K, T[T_CURL]), T[T_CURL].threads, 0, s>>>(g, b.vn, b.zeta, T[T_CURL].kb));
-  LAUNCH(K_VT_P, k_vt<R><<<grid2(g.ne, K, T[T_VT]), T[T_VT].threads, 0, s>>>(g, b.vn, b.vt, T[T_VT].kb));
-  LAUNCH(K_CELL_P, k_cell_adv<R, false><<<grid2(g.nc, K + 1, T[T_CELLADV]), T[T_CELLADV].threads, 0, s>>>(
-                       g, b.vn, b.vt, b.w, b.kc, b.tw0, nullptr, T[T_CELLADV].kb));
+  const Tile& tv = T[T_VC];
+  const int ncb = (g.nc + tv.threads - 1) / tv.threads;
+  const dim3 gvc(ncb + (g.nv + tv.threads - 1) / tv.threads, (K + tv.kb - 1) / tv.kb);
+  LAUNCH(K_VC_P, k_vc<R, false><<<gvc, tv.threads, 0, s>>>(g, b.vn, b.zeta, b.kc, nullptr, ncb, tv.kb));
   LAUNCH(K_EDGE_P, k_edge<R, false><<<grid2(g.ne, K, T[T_EDGE]), T[T_EDGE].threads, 0, s>>>(
-                       g, b.vn, b.vt, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, c, T[T_EDGE].kb));
-  const int ncol = (g.nc + T[T_COL].threads - 1) / T[T_COL].threads;
-  LAUNCH(K_COL_P, k_col<R, false><<<ncol, T[T_COL].threads, 0, s>>>(g, b.w, b.rho, b.ex, b.th, b.vns, b.tw0, nullptr,
-                                                                      b.ws, nullptr, nullptr, nullptr, b.cp, b.dp,
-                                                                      nullptr, nullptr, c));
+                       g, b.vn, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, c, T[T_EDGE].kb));
+  ColArgs<R> ca{b.w, b.rho, b.ex, b.th, b.vn, b.vns, nullptr, nullptr, b.ws, nullptr, nullptr, nullptr};
+  LAUNCH(K_COL_P, launch_col<R, false>(g, ca, c, s));
   // corrector: tendencies at the predicted state, damping, momentum, column
-  LAUNCH(K_CURL_C, k_curl<R><<<grid2(g.nv, K, T[T_CURL]), T[T_CURL].threads, 0, s>>>(g, b.vns, b.zeta, T[T_CURL].kb));
-  LAUNCH(K_VT_C, k_vt<R><<<grid2(g.ne, K, T[T_VT]), T[T_VT].threads, 0, s>>>(g, b.vns, b.vt, T[T_VT].kb));
-  LAUNCH(K_CELL_C, k_cell_adv<R, true><<<grid2(g.nc, K + 1, T[T_CELLADV]), T[T_CELLADV].threads, 0, s>>>(
-                       g, b.vns, b.vt, b.ws, b.kc, b.tw1, b.d2, T[T_CELLADV].kb));
+  LAUNCH(K_VC_C, k_vc<R, true><<<gvc, tv.threads, 0, s>>>(g, b.vns, b.zeta, b.kc, b.d2, ncb, tv.kb));
   LAUNCH(K_EDGE_C, k_edge<R, true><<<grid2(g.ne, K, T[T_EDGE]), T[T_EDGE].threads, 0, s>>>(
-                       g, b.vns, b.vt, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, c, T[T_EDGE].kb));
-  LAUNCH(K_COL_C, k_col<R, true><<<ncol, T[T_COL].threads, 0, s>>>(g, b.w, b.rho, b.ex, b.th, b.vn_out, b.tw0, b.tw1,
-                                                                     b.w_out, b.rho_out, b.ex_out, b.th_out, b.cp, b.dp,
-                                                                     b.drx, b.dxx, c));
+                       g, b.vns, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, c, T[T_EDGE].kb));
+  ColArgs<R> cc{b.w, b.rho, b.ex, b.th, b.vn, b.vn_out, b.vns, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out};
+  LAUNCH(K_COL_C, launch_col<R, true>(g, cc, c, s));
 }
 
 template <typename R>
