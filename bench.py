@@ -90,6 +90,70 @@ def cpu_baseline(spec, g0, S, vert, budget_s=25.0):
                       f"{os.cpu_count()}"}
 
 
+def bench_ensemble(args, D, torch):
+    """24 uneven members (12 x R2B4 + 12 x R2B5, 65 levels, mixed precision):
+    one graph launch per step against a loop of per-member steps."""
+    from synth import ensemble_member, initial_state, make_grid
+
+    grids, states, cells = {}, [], 0
+    spec = ensemble_member(0)
+    for m in range(24):
+        sp = ensemble_member(m)
+        if sp["k"] not in grids:
+            g = make_grid(sp["n"], sp["k"])
+            _, vert = initial_state(g, sp["n_lev"], sp["z_top"], seed=0)
+            grids[sp["k"]] = (g, D.Grid(g, vert))
+        g, G = grids[sp["k"]]
+        S, _ = initial_state(g, sp["n_lev"], sp["z_top"], **sp["state"])
+        st = D.State(G, precision="mixed")
+        st.write(S)
+        states.append(st)
+        cells += g["n_cells"] * sp["n_lev"]
+    dt, nsub = spec["dt"], spec["nsub"]
+    E = D.Ensemble(states)
+    cache = os.environ.get("DC_SCHEDULE_CACHE", "/tmp/dycore_schedules.txt")
+    t0 = time.perf_counter()
+    E.autotune(dt, nsub, cache)
+    tune_s = time.perf_counter() - t0
+    sched = E.schedule()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_graph = timed(lambda: E.step(dt, nsub), args.steps)
+    E.close()
+
+    def loop():
+        for st in states:
+            st.step(dt, nsub)
+
+    ms_loop = timed(loop, args.steps)
+    line = {"metric": METRIC, "value": cells / (ms_graph * 1e-3), "unit": "cell·level·steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "ensemble: 12 x R2B4 + 12 x R2B5 members, 65 levels, mixed precision, "
+                                   f"dt {dt} s, {nsub} substeps, one graph launch per step",
+                       "members": 24, "cell_levels": cells},
+            "per_member_loop": {"ms_per_step": ms_loop, "value": cells / (ms_loop * 1e-3)},
+            "speedup_vs_loop": ms_loop / ms_graph, "schedule": sched,
+            "autotune_s": tune_s}
+    for st in states:
+        st.close()
+    for _, G in grids.values():
+        G.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +188,8 @@ def main():
     from paper_2608_21150_amd import dycore as D
     from synth import WORKLOADS, build_workload
 
+    if args.workload == "ensemble":
+        return bench_ensemble(args, D, torch)
     spec = WORKLOADS[args.workload]
     sfc = bool(spec.get("sfc", 0)) if args.sfc < 0 else bool(args.sfc)
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)

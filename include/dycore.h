@@ -200,12 +200,30 @@ typedef struct {
 dc_status dc_state_profile(dc_state *st, int32_t enable);
 dc_status dc_state_profile_read(dc_state *st, dc_kernel_stat *out, int32_t cap, int32_t *n_out);
 
-/* Batched ensemble: members (any grids, same precision) stepped together by
- * one hipGraph launch whose kernels each cover every member through a
- * per-launch work table.  Members keep their own buffers and stream-less
- * semantics: the graph is launched on the first member's stream. */
+/* Batched ensemble (paper, Section 4.3.3: launch overhead must not show).
+ * Members on any grids, sharing precision, n_lev and diffusion mode, and
+ * starting in the same buffer set, advance together: every phase of the
+ * step is one persistent kernel whose blocks walk a (member, tile) work
+ * table, and the whole step is captured into a hipGraph (cached per dt,
+ * nsubsteps and buffer set) that dc_ensemble_step replays with one
+ * hipGraphLaunch on a stream the ensemble owns; events order it after work
+ * already queued on the members' streams and later member work after it.  Members keep their own buffers and stay
+ * valid single states; stepping a member alone in between makes
+ * dc_ensemble_step return DC_ESTATE until the buffer sets agree again.
+ * Each member's result is bit-identical to stepping it alone.
+ * Destroy the ensemble before its members. */
 dc_status dc_ensemble_create(dc_state *const *members, int32_t n_members, dc_ensemble **out);
 dc_status dc_ensemble_step(dc_ensemble *ens, double dt, int32_t nsubsteps);
+/* The same step launched eagerly (no graph), synchronising. */
+dc_status dc_ensemble_step_eager(dc_ensemble *ens, double dt, int32_t nsubsteps);
+/* Pick the tile/grid schedule of every phase by timing candidates on the
+ * ensemble itself (members' states are restored afterwards).  cache_path
+ * (may be NULL): a text file of "key<TAB>schedule" lines; a matching key is
+ * reused without timing, a new result is appended. */
+dc_status dc_ensemble_autotune(dc_ensemble *ens, double dt, int32_t nsubsteps, const char *cache_path);
+/* Text form of the current schedule ("threads x levels" per tile kind, then
+ * blocks per CU of every phase, 0 = one block per tile). */
+dc_status dc_ensemble_schedule(const dc_ensemble *ens, char *buf, size_t n);
 dc_status dc_ensemble_destroy(dc_ensemble *ens);
 
 /* Thread-local message of the last failing call ("" if none). */

@@ -16,6 +16,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "state.h"
 
 namespace dc {
 
@@ -25,33 +26,6 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 }  // namespace dc
 
 using namespace dc;
-
-struct dc_grid {
-  HostGrid h;
-  DevGrid d{};
-  bool uploaded = false;
-  int device = -1;
-  std::vector<void*> allocs;
-  std::atomic<int> states{0};
-};
-
-struct dc_state {
-  dc_grid* grid = nullptr;
-  dc_params p{};
-  dc_precision prec = DC_PREC_FP64;
-  dc_diffusion diff = DC_DIFF_PLAIN;
-  dc_fields buf[2]{};
-  int cur = 0;
-  hipStream_t stream = nullptr;
-  DevGrid d{};  // grid view plus per-state Coriolis and sponge tables
-  Tile tiles[T_COUNT];
-  Prof prof;
-  // workspace carve-up
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
-  double *wstar, *wtmp, *fe, *tau, *diag_part, *diag_out;
-};
 
 namespace {
 
@@ -183,67 +157,12 @@ void* field_ptr(const dc_fields& f, int field) {
   }
 }
 
-void default_tiles(const HostGrid& h, Tile* t) {
-  // levels per block so that each launch has a few thousand blocks when the
-  // grid is large, and one level per block on small grids
-  auto kb_for = [&](int n, int levels) {
-    const int nbx = (n + 255) / 256;
-    int kb = (int)((long long)levels * nbx / 2048);
-    return std::max(1, std::min(kb, 16));
-  };
-  t[T_VC] = {256, kb_for(h.nc + h.nv, h.K)};
-  t[T_EDGE] = {256, kb_for(h.ne, h.K)};
-  t[T_DVERT] = {256, kb_for(h.nv, h.K)};
-  t[T_DCELL] = {256, kb_for(h.nc + h.nv, h.K + 1)};
-  t[T_DEDGE] = {256, kb_for(h.ne, h.K)};
-}
-
-StepCoef make_coef(const dc_state* s, double dt, int nsub) {
-  StepCoef c{};
-  c.dtau = dt / nsub;
-  c.dt = dt;
-  c.eta = s->p.eta;
-  c.a0 = s->p.adv_w0;
-  c.a1 = s->p.adv_w1;
-  c.cpd = s->p.cpd;
-  c.rd_cvd = s->p.rd / s->p.cvd;
-  c.cvd_rd = s->p.cvd / s->p.rd;
-  c.c4a2 = s->p.divdamp_c4 * s->grid->h.mean_area * s->grid->h.mean_area;
-  c.cs = s->p.smag_cs;
-  c.cap = s->p.smag_cap;
-  c.k4 = s->p.hdiff_k4;
-  c.diffuse_w = s->p.diffuse_w;
-  return c;
-}
-
 template <typename R>
 void enqueue_step(dc_state* s, double dt, int nsub) {
   const StepCoef c = make_coef(s, dt, nsub);
   const bool diffuse = s->diff != DC_DIFF_NONE;
   for (int i = 0; i < nsub; ++i) {
-    const dc_fields& cur = s->buf[s->cur];
-    const dc_fields& nxt = s->buf[1 - s->cur];
-    const bool last = i == nsub - 1;
-    Bufs<R> b{};
-    b.vn = static_cast<const R*>(cur.vn);
-    b.w = static_cast<const double*>(cur.w);
-    b.rho = static_cast<const double*>(cur.rho);
-    b.ex = static_cast<const double*>(cur.exner);
-    b.th = static_cast<const double*>(cur.theta_v);
-    b.vt = static_cast<R*>(s->vt);
-    b.tvn0 = static_cast<R*>(s->tvn0);
-    b.vns = static_cast<R*>(s->vns);
-    b.kc = static_cast<R*>(s->kc);
-    b.d2 = static_cast<R*>(s->d2);
-    b.zeta = static_cast<R*>(s->zeta);
-    b.vv = static_cast<R*>(s->vv);
-    b.ws = s->wstar;
-    b.wtmp = s->wtmp;
-    b.vn_out = static_cast<R*>(nxt.vn);
-    b.w_out = (last && diffuse) ? s->wtmp : static_cast<double*>(nxt.w);
-    b.rho_out = static_cast<double*>(nxt.rho);
-    b.ex_out = static_cast<double*>(nxt.exner);
-    b.th_out = static_cast<double*>(nxt.theta_v);
+    const Bufs<R> b = substep_bufs<R>(s, s->cur, i == nsub - 1 && diffuse);
     launch_substep<R>(s->d, b, c, s->tiles, s->stream, &s->prof);
     s->cur ^= 1;
   }
@@ -589,12 +508,5 @@ dc_status dc_state_destroy(dc_state* s) {
   if (e != hipSuccess) return fail(DC_EHIP, std::string("pending work failed: ") + hipGetErrorString(e));
   return DC_OK;
 }
-
-dc_status dc_ensemble_create(dc_state* const*, int32_t, dc_ensemble** out) {
-  if (out) *out = nullptr;
-  return fail(DC_ESTATE, "ensemble stepping is not available in this build");
-}
-dc_status dc_ensemble_step(dc_ensemble*, double, int32_t) { return fail(DC_ESTATE, "ensemble stepping is not available in this build"); }
-dc_status dc_ensemble_destroy(dc_ensemble*) { return fail(DC_ESTATE, "ensemble stepping is not available in this build"); }
 
 }  // extern "C"

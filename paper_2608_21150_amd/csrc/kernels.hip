@@ -1,20 +1,10 @@
-// HIP kernels (gfx950) of the non-hydrostatic dycore step.
-//
-// Layout: every field is [level][entity], entity index fastest, each level
-// padded to a multiple of 64 entities; a thread owns one entity and walks a
-// block of levels, so the neighbour indices and stencil weights are loaded
-// once per thread and every level access of the own entity is a coalesced
-// 64-wide row.  Gathers go through the lookup tables (paper, Section 4.2.1).
-// Blocks are remapped so that the 8 XCDs each sweep a contiguous range of
-// tiles (neighbour halos then mostly hit the same XCD's L2).
-//
-// Template parameter R is the type of vn and of the horizontal-stencil
-// intermediates: double for the FP64 path, float for the mixed path.  The
-// column solver, w/rho/exner/theta_v and flux-divergence sums are always
-// FP64.  No floating-point atomics: results do not depend on scheduling.
+// Single-state launches of the dycore step (see bodies.h for the kernels).
+
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "bodies.h"
 #include "internal.h"
 #include "kernels.h"
 
@@ -22,699 +12,7 @@ namespace dc {
 
 namespace {
 
-__device__ __forceinline__ void tile_coords(int& bx, int& by) {
-  const int nbx = gridDim.x;
-  const int n = gridDim.x * gridDim.y;
-  const int lin = blockIdx.x + blockIdx.y * nbx;
-  const int q = n >> 3, r = n & 7, x = lin & 7, i = lin >> 3;
-  const int lp = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-  bx = lp % nbx;
-  by = lp / nbx;
-}
-
-__device__ __forceinline__ const double* vt_row(const DevGrid& g, int tab) { return g.vert + (size_t)tab * (g.K + 1); }
-
-// ---------------------------------------------------------------------------
-// Tangential wind at edge e by Perot reconstruction: a 5-point stencil over
-// the edge and its four e2c2e neighbours (weights precomputed on the host).
-// ---------------------------------------------------------------------------
-template <typename R>
-struct VtStencil {
-  int idx[4];
-  R w[5];
-  __device__ __forceinline__ void load(const DevGrid& g, int e) {
-    w[0] = (R)g.kvt[e];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      idx[s] = g.e2c2e[s * g.es + e];
-      w[1 + s] = (R)g.kvt[(1 + s) * g.es + e];
-    }
-  }
-  __device__ __forceinline__ R apply(const R* __restrict__ row, int e) const {
-    R acc = w[0] * row[e];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc += w[1 + s] * row[idx[s]];
-    return acc;
-  }
-};
-
-// ---------------------------------------------------------------------------
-// vertex + cell pass (one launch, blocks [0, ncb) are cells):
-//  vertices: relative vorticity zeta_v = (1/A_v) sum sig d_e vn_e
-//  cells:    kinetic energy K_c = mean over the 3 edges of (vn^2 + vt^2)/2,
-//            vt reconstructed in place; in the corrector also the
-//            divergence-damping field D2 = laps(div vn).
-// ---------------------------------------------------------------------------
-template <typename R, bool CORR>
-__global__ void __launch_bounds__(256) k_vc(DevGrid g, const R* __restrict__ vn, R* __restrict__ zeta,
-                                            R* __restrict__ kc, R* __restrict__ d2, int ncb, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-  if (bx >= ncb) {
-    const int v = (bx - ncb) * blockDim.x + threadIdx.x;
-    if (v >= g.nv) return;
-    int idx[6];
-    R cf[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      idx[s] = g.v2e[s * g.vs + v];
-      cf[s] = (R)g.kcurl[s * g.vs + v];
-    }
-    for (int k = k0; k < k1; ++k) {
-      const R* row = vn + (size_t)k * g.es;
-      R acc = cf[0] * row[idx[0]];
-#pragma unroll
-      for (int s = 1; s < 6; ++s) acc += cf[s] * row[idx[s]];
-      zeta[(size_t)k * g.vs + v] = acc;
-    }
-    return;
-  }
-  const int c = bx * blockDim.x + threadIdx.x;
-  if (c >= g.nc) return;
-  int ie[3], nb[3];
-  R kd[3];
-  VtStencil<R> vts[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    ie[i] = g.c2e[i * g.cs + c];
-    nb[i] = g.c2e2c[i * g.cs + c];
-    kd[i] = (R)g.kdiv[i * g.cs + c];
-    vts[i].load(g, ie[i]);
-  }
-  int ie2[3][3];
-  R kd2[3][3], kl[3];
-  if (CORR) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      kl[i] = (R)g.klap[i * g.cs + c];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        ie2[i][m] = g.c2e[m * g.cs + nb[i]];
-        kd2[i][m] = (R)g.kdiv[m * g.cs + nb[i]];
-      }
-    }
-  }
-  for (int k = k0; k < k1; ++k) {
-    const R* vrow = vn + (size_t)k * g.es;
-    R ke = R(0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const R a = vrow[ie[i]], b = vts[i].apply(vrow, ie[i]);
-      ke += R(0.5) * (a * a + b * b);
-    }
-    kc[(size_t)k * g.cs + c] = ke / R(3);
-    if (CORR) {
-      const R dc = kd[0] * vrow[ie[0]] + kd[1] * vrow[ie[1]] + kd[2] * vrow[ie[2]];
-      R acc = R(0);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const R dn = kd2[i][0] * vrow[ie2[i][0]] + kd2[i][1] * vrow[ie2[i][1]] + kd2[i][2] * vrow[ie2[i][2]];
-        acc += kl[i] * (dn - dc);
-      }
-      d2[(size_t)k * g.cs + c] = acc;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// edge: advective tendency T_vn and the horizontal momentum update.
-//  predictor: vn* = vn + dtau (T_vn - cpd theta_e grad pi')       -> tvn0, vns
-//  corrector: vn' = vn_now + dtau (a0 T0 + a1 T* - cpd theta_e grad pi')
-//                   - c4 Abar^2 grad(D2)                             -> vn_out
-// The pressure-gradient term is formed from the state at the start of the
-// substep in both passes.
-// ---------------------------------------------------------------------------
-template <typename R, bool CORR>
-__global__ void __launch_bounds__(256) k_edge(DevGrid g, const R* __restrict__ vn, const R* __restrict__ zeta, const R* __restrict__ kc,
-                                              const double* __restrict__ w, const double* __restrict__ ex,
-                                              const double* __restrict__ th, R* __restrict__ tvn0,
-                                              R* __restrict__ vout, const R* __restrict__ vn_now,
-                                              const R* __restrict__ d2, StepCoef cf, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int e = bx * blockDim.x + threadIdx.x;
-  if (e >= g.ne) return;
-  const int K = g.K;
-  const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
-  const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
-  const double invd = g.invd[e];
-  const R invd_r = (R)invd;
-  const R fe = (R)g.fe[e];
-  VtStencil<R> vts;
-  vts.load(g, e);
-  const double* idzf = vt_row(g, VT_IDZF);
-  const double* exref = vt_row(g, VT_EXREF);
-  const int k0 = by * kb, k1 = min(K, k0 + kb);
-  for (int j = k0; j < k1; ++j) {
-    const size_t re = (size_t)j * g.es + e;
-    const R vj = vn[re];
-    const R vup = j > 0 ? vn[re - g.es] : vj;
-    const R vdn = j < K - 1 ? vn[re + g.es] : vj;
-    const R ie_top = j > 0 ? R(0.5) * (vup + vj) : vj;
-    const R ie_bot = j < K - 1 ? R(0.5) * (vj + vdn) : vj;
-    const R* zr = zeta + (size_t)j * g.vs;
-    const R ze = R(0.5) * (zr[v0] + zr[v1]);
-    const R* kr = kc + (size_t)j * g.cs;
-    const R kgrad = (kr[c1] - kr[c0]) * invd_r;
-    const double* wa = w + (size_t)j * g.cs;
-    const double* wb = wa + g.cs;
-    const R wef = (R)(0.5 * (0.5 * (wa[c0] + wa[c1]) + 0.5 * (wb[c0] + wb[c1])));
-    const R vt = vts.apply(vn + (size_t)j * g.es, e);
-    const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
-    const size_t rc = (size_t)j * g.cs;
-    const double exr = exref[j];
-    const R gex = (R)((ex[rc + c1] - exr) - (ex[rc + c0] - exr)) * invd_r;
-    const R the = (R)(0.5 * (th[rc + c0] + th[rc + c1]));
-    const R pgf = (R)cf.cpd * the * gex;
-    if (!CORR) {
-      tvn0[re] = tvn;
-      vout[re] = vj + (R)cf.dtau * (tvn - pgf);
-    } else {
-      const R dd = (d2[rc + c1] - d2[rc + c0]) * invd_r;
-      vout[re] = vn_now[re] + (R)cf.dtau * ((R)cf.a0 * tvn0[re] + (R)cf.a1 * tvn - pgf) - (R)cf.c4a2 * dd;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// column: vertical-wind advection T_w, flux divergences, explicit parts, the
-// tridiagonal w solve, sponge and (corrector) the increment updates of rho,
-// exner and theta_v.
-// Layout: a block holds 64 neighbouring columns (one per lane, so every
-// level row is one coalesced 512-byte access) and P waves; wave p owns a
-// chunk of at most LM consecutive half levels (rows) of those columns.
-// Solve: partition method.  Each wave eliminates its chunk in registers
-// (down sweep, then up sweep), leaving every row expressed through the last
-// row of the chunk above and the first row of the chunk below; the interface
-// unknowns form a 2x2-block tridiagonal system of P-1 blocks that wave 0
-// solves through LDS; every wave then back-substitutes its rows.  The matrix
-// is diagonally similar to I + symmetric positive semi-definite, so no
-// pivoting is needed anywhere.  No HBM scratch.  Rows 0 and K are the w = 0
-// boundaries.
-// ---------------------------------------------------------------------------
-template <typename R>
-struct ColArgs {
-  const double *w, *rho, *ex, *th;  // state at the start of the substep
-  const R* vn;                       // vn at the start of the substep (T_w)
-  const R* vnf;                      // vn of the mass fluxes (vn* / new vn)
-  const R* vns;                      // corrector: predicted vn* (T_w*)
-  const double* ws;                  // corrector: predicted w* (T_w*)
-  double *w_out, *rho_out, *ex_out, *th_out;
-};
-
-// T_w at half level k (1 <= k <= K-1) of column c from vn and w (w_up, w_k,
-// w_dn: the column's own w at half levels k-1, k, k+1).
-template <typename R>
-__device__ __forceinline__ double col_tw(const DevGrid& g, const R* __restrict__ vn, const double* __restrict__ w,
-                                         double w_up, double w_k, double w_dn, int k, const int* ie, const int* nb,
-                                         const R* kd) {
-  const R* va = vn + (size_t)(k - 1) * g.es;
-  const R* vb = vn + (size_t)k * g.es;
-  const double* wr = w + (size_t)k * g.cs;
-  R hs = R(0);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const R vie = R(0.5) * (va[ie[i]] + vb[ie[i]]);
-    hs += kd[i] * vie * (R)(wr[nb[i]] - w_k);
-  }
-  const double dwdz = (w_up - w_dn) * vt_row(g, VT_IDZC2)[k];
-  return (double)(R(-0.5) * hs - (R)(w_k * dwdz));
-}
-
-// State of one level of a column: full level j and half level j.
-struct ColLev {
-  double rho, th, ex, thp, exp_;  // full level j
-  double w, ws;                    // w, w* at half level j
-  double ric, atil, gam, zth;      // half level j
-};
-
-__device__ __forceinline__ void col_load(const DevGrid& g, const double* __restrict__ rho,
-                                         const double* __restrict__ th, const double* __restrict__ ex, int j, int c,
-                                         ColLev& L) {
-  const size_t r = (size_t)j * g.cs + c;
-  L.rho = rho[r];
-  L.th = th[r];
-  L.ex = ex[r];
-  L.thp = L.th - vt_row(g, VT_THREF)[j];
-  L.exp_ = L.ex - vt_row(g, VT_EXREF)[j];
-}
-
-// half-level quantities of level b (= j1) from full levels j1-1 (a) and j1 (b)
-__device__ __forceinline__ void col_half(const DevGrid& g, const ColLev& a, ColLev& b, int j1, double dtau,
-                                         double cpd, double eta) {
-  b.ric = 0.5 * (a.rho + b.rho);
-  const double thp_ic = 0.5 * (a.thp + b.thp);
-  const double th_ic = vt_row(g, VT_THREFIC)[j1] + thp_ic;
-  b.atil = th_ic * b.ric;
-  const double idzh = vt_row(g, VT_IDZH)[j1];
-  b.gam = dtau * cpd * eta * th_ic * idzh;
-  b.zth = (1.0 - eta) * th_ic * (a.exp_ - b.exp_) * idzh + thp_ic * vt_row(g, VT_DEXREFIC)[j1];
-}
-
-template <typename R, bool CORR, int LM>
-__global__ void __launch_bounds__(512) k_colq(DevGrid g, ColArgs<R> a, StepCoef cf, int P) {
-  extern __shared__ double s_red[];  // [6][P][64]
-  const int K = g.K, cs = g.cs;
-  const int cl = threadIdx.x & 63, p = threadIdx.x >> 6;
-  int bx, by;
-  tile_coords(bx, by);
-  const int c0 = bx * 64 + cl;
-  const bool ok = c0 < g.nc;
-  const int c = ok ? c0 : 0;  // padding lanes compute column 0 and store nothing
-  // rows (half levels 1..K-1) of this chunk: [s, s + n)
-  const int nrow = K - 1;
-  const int base = nrow / P, extra = nrow - base * P;
-  const int n = base + (p < extra ? 1 : 0);
-  const int s = 1 + p * base + min(p, extra);
-  const int h = s - 1;  // full level above the first row (halo; chunk 0 owns it)
-  const double* idzf = vt_row(g, VT_IDZF);
-  const double eta = cf.eta, dtau = cf.dtau, cpd = cf.cpd, oneme = 1.0 - eta;
-  int ie[3], nb[3];
-  double kd[3];
-  R kdr[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    ie[q] = g.c2e[q * cs + c];
-    nb[q] = g.c2e2c[q * cs + c];
-    kd[q] = g.kdiv[q * cs + c];
-    kdr[q] = (R)kd[q];
-  }
-
-  // ---- forward sweep over levels h..h+n: explicit parts, rows, down sweep ----
-  double cpv[LM], dpv[LM], lpv[LM];
-  double drxv[LM + 1], dxxv[LM + 1];
-  ColLev cur;
-  col_load(g, a.rho, a.th, a.ex, h, c, cur);
-  cur.w = a.w[(size_t)h * cs + c];
-  cur.ws = CORR ? a.ws[(size_t)h * cs + c] : 0.0;
-  double w_up = 0.0, ws_up = 0.0;
-  if (h >= 1) {
-    ColLev up;
-    col_load(g, a.rho, a.th, a.ex, h - 1, c, up);
-    col_half(g, up, cur, h, dtau, cpd, eta);
-    w_up = a.w[(size_t)(h - 1) * cs + c];
-    if (CORR) ws_up = a.ws[(size_t)(h - 1) * cs + c];
-  } else {
-    cur.ric = cur.rho;
-    cur.atil = 0.0;
-    cur.gam = 0.0;
-    cur.zth = 0.0;
-  }
-  double beta_p = 0.0, e_p = 0.0, atil_p = 0.0;
-#pragma unroll
-  for (int i = 0; i <= LM; ++i) {
-    if (i <= n) {
-      const int j = h + i;
-      ColLev nx;
-      if (j + 1 < K) {
-        col_load(g, a.rho, a.th, a.ex, j + 1, c, nx);
-        col_half(g, cur, nx, j + 1, dtau, cpd, eta);
-        nx.w = a.w[(size_t)(j + 1) * cs + c];
-        nx.ws = CORR ? a.ws[(size_t)(j + 1) * cs + c] : 0.0;
-      } else {
-        nx.ric = cur.rho;
-        nx.atil = 0.0;
-        nx.w = a.w[(size_t)K * cs + c];
-        nx.ws = 0.0;
-      }
-      // mass and theta fluxes, explicit parts at full level j
-      double dm = 0.0, dth = 0.0;
-      {
-        const R* vr = a.vnf + (size_t)j * g.es;
-        const double* rr = a.rho + (size_t)j * cs;
-        const double* tr = a.th + (size_t)j * cs;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const R rho_e = (R)(0.5 * (cur.rho + rr[nb[q]]));
-          const R th_e = (R)(0.5 * (cur.th + tr[nb[q]]));
-          const R fm = rho_e * vr[ie[q]];
-          const R ft = fm * th_e;
-          dm += kd[q] * (double)fm;
-          dth += kd[q] * (double)ft;
-        }
-      }
-      const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
-      const double beta = b * idzf[j];
-      const double drx = -dtau * (dm + oneme * (cur.ric * cur.w - nx.ric * nx.w) * idzf[j]);
-      const double dxx = -b * (dth + oneme * (cur.atil * cur.w - nx.atil * nx.w) * idzf[j]);
-      const double e_c = cur.exp_ + dxx;
-      drxv[i] = drx;
-      dxxv[i] = dxx;
-      if (i >= 1) {
-        // row of half level j, then one step of the down sweep
-        double tw = col_tw<R>(g, a.vn, a.w, w_up, cur.w, nx.w, j, ie, nb, kdr);
-        if (CORR) tw = cf.a0 * tw + cf.a1 * col_tw<R>(g, a.vns, a.ws, ws_up, cur.ws, nx.ws, j, ie, nb, kdr);
-        const double wx = cur.w + dtau * (tw - cpd * cur.zth);
-        const double A = -cur.gam * beta_p * (eta * atil_p);
-        const double B = 1.0 + cur.gam * (eta * cur.atil) * (beta_p + beta);
-        const double C = -cur.gam * beta * (eta * nx.atil);
-        const double rhs = wx - cur.gam * (e_p - e_c);
-        if (i == 1) {
-          cpv[0] = C / B;
-          dpv[0] = rhs / B;
-          lpv[0] = A / B;
-        } else {
-          const double den = B - A * cpv[i - 2];
-          cpv[i - 1] = C / den;
-          dpv[i - 1] = (rhs - A * dpv[i - 2]) / den;
-          lpv[i - 1] = -A * lpv[i - 2] / den;
-        }
-      }
-      beta_p = beta;
-      e_p = e_c;
-      atil_p = cur.atil;
-      w_up = cur.w;
-      ws_up = cur.ws;
-      cur = nx;
-    }
-  }
-  // ---- up sweep: row i of the chunk = d_i - u_i x_below - v_i x_above ----
-#pragma unroll
-  for (int i = LM - 2; i >= 0; --i) {
-    if (i < n - 1) {
-      dpv[i] = dpv[i] - cpv[i] * dpv[i + 1];
-      lpv[i] = lpv[i] - cpv[i] * lpv[i + 1];
-      cpv[i] = -cpv[i] * cpv[i + 1];
-    }
-  }
-  // ---- interface system (2x2 blocks), solved by wave 0 ----
-  const int sP = P * 64;
-  double xa = 0.0, xb = 0.0;  // x in the last row of the chunk above, first row of the chunk below
-  if (P > 1) {
-    double dl = 0.0, ul = 0.0, vl = 0.0;
-#pragma unroll
-    for (int i = 0; i < LM; ++i)
-      if (i == n - 1) {
-        dl = dpv[i];
-        ul = cpv[i];
-        vl = lpv[i];
-      }
-    const int o = p * 64 + cl;
-    s_red[0 * sP + o] = dl;
-    s_red[1 * sP + o] = ul;
-    s_red[2 * sP + o] = vl;
-    s_red[3 * sP + o] = dpv[0];
-    s_red[4 * sP + o] = cpv[0];
-    s_red[5 * sP + o] = lpv[0];
-    __syncthreads();
-    if (p == 0) {
-      double c0p = 0.0, g0p = 0.0;
-      for (int q = 0; q < P - 1; ++q) {
-        const int oq = q * 64 + cl, on = (q + 1) * 64 + cl;
-        const double dz = s_red[0 * sP + oq], uz = s_red[1 * sP + oq], vz = s_red[2 * sP + oq];
-        const double df = s_red[3 * sP + on], uf = s_red[4 * sP + on], vf = s_red[5 * sP + on];
-        const double bq = uz - vz * c0p;
-        const double det = 1.0 - bq * vf;
-        const double r0 = dz - vz * g0p, r1 = df;
-        const double g0 = (r0 - bq * r1) / det, g1 = (r1 - vf * r0) / det;
-        const double k0 = -bq * uf / det, k1 = uf / det;
-        s_red[0 * sP + oq] = k0;
-        s_red[1 * sP + oq] = k1;
-        s_red[2 * sP + oq] = g0;
-        s_red[3 * sP + oq] = g1;
-        c0p = k0;
-        g0p = g0;
-      }
-      double fnext = 0.0;
-      for (int q = P - 2; q >= 0; --q) {
-        const int oq = q * 64 + cl;
-        const double y0 = s_red[2 * sP + oq] - s_red[0 * sP + oq] * fnext;
-        const double y1 = s_red[3 * sP + oq] - s_red[1 * sP + oq] * fnext;
-        s_red[4 * sP + oq] = y0;  // last row of chunk q
-        s_red[5 * sP + oq] = y1;  // first row of chunk q + 1
-        fnext = y1;
-      }
-    }
-    __syncthreads();
-    if (p > 0) xa = s_red[4 * sP + (p - 1) * 64 + cl];
-    if (p < P - 1) xb = s_red[5 * sP + p * 64 + cl];
-  }
-  // ---- back substitution and sponge: w* at half levels s..s+n-1 ----
-  // (row i of the chunk is half level s + i; w*(h) of the chunk above is
-  // needed only by chunk 0, where it is the w = 0 boundary)
-  const int e = s + n;
-  const double w_below = (e < K) ? xb / (1.0 + dtau * g.tau[e]) : 0.0;
-  if (!CORR) {
-#pragma unroll
-    for (int i = 0; i < LM; ++i) {
-      if (i < n && ok) {
-        const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
-        a.w_out[(size_t)(s + i) * cs + c] = x / (1.0 + dtau * g.tau[s + i]);
-      }
-    }
-  }
-  if (ok && p == 0) a.w_out[c] = 0.0;
-  if (ok && p == P - 1) a.w_out[(size_t)K * cs + c] = 0.0;
-
-  // ---- corrector: w*, and increment updates of rho, exner, theta_v at
-  // full levels h..h+n (level h only in chunk 0) ----
-  if (CORR) {
-    ColLev lv;
-    col_load(g, a.rho, a.th, a.ex, h, c, lv);
-    if (h >= 1) {
-      ColLev up;
-      col_load(g, a.rho, a.th, a.ex, h - 1, c, up);
-      col_half(g, up, lv, h, dtau, cpd, eta);
-    } else {
-      lv.ric = lv.rho;
-      lv.atil = 0.0;
-    }
-    double w0 = 0.0;  // w* at half level h (used by chunk 0 only: the top boundary)
-#pragma unroll
-    for (int i = 0; i <= LM; ++i) {
-      if (i <= n) {
-        const int j = h + i;
-        double w1 = w_below;
-        if (i < n) {
-          const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
-          w1 = x / (1.0 + dtau * g.tau[s + i]);
-          if (ok) a.w_out[(size_t)(s + i) * cs + c] = w1;
-        }
-        ColLev nx;
-        if (j + 1 < K) {
-          col_load(g, a.rho, a.th, a.ex, j + 1, c, nx);
-          col_half(g, lv, nx, j + 1, dtau, cpd, eta);
-        } else {
-          nx.ric = lv.rho;
-          nx.atil = 0.0;
-        }
-        if (i >= 1 || p == 0) {
-          const double b = dtau * cf.rd_cvd * lv.ex / (lv.rho * lv.th);
-          const double beta = b * idzf[j];
-          const double drho = drxv[i] - dtau * eta * (lv.ric * w0 - nx.ric * w1) * idzf[j];
-          const double dex = dxxv[i] - beta * (eta * lv.atil * w0 - eta * nx.atil * w1);
-          const double rho_new = lv.rho + drho;
-          if (ok) {
-            const size_t r = (size_t)j * cs + c;
-            a.rho_out[r] = rho_new;
-            a.ex_out[r] = lv.ex + dex;
-            a.th_out[r] = lv.th + (lv.rho * lv.th * cf.cvd_rd * dex / lv.ex - lv.th * drho) / rho_new;
-          }
-        }
-        w0 = w1;
-        lv = nx;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// diffusion
-// ---------------------------------------------------------------------------
-// vertex: least-squares vertex vector V_v (3 components) and vorticity.
-template <typename R>
-__global__ void __launch_bounds__(256) k_dvert(DevGrid g, const R* __restrict__ vn, R* __restrict__ vv,
-                                               R* __restrict__ zeta, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int v = bx * blockDim.x + threadIdx.x;
-  if (v >= g.nv) return;
-  int idx[6];
-  R cc[6], lw[3][6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    idx[s] = g.v2e[s * g.vs + v];
-    cc[s] = (R)g.kcurl[s * g.vs + v];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) lw[j][s] = (R)g.klsq[(j * 6 + s) * g.vs + v];
-  }
-  const size_t plane = (size_t)g.K * g.vs;
-  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-  for (int k = k0; k < k1; ++k) {
-    const R* row = vn + (size_t)k * g.es;
-    R x[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) x[s] = row[idx[s]];
-    R z = R(0), a = R(0), b = R(0), d = R(0);
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      z += cc[s] * x[s];
-      a += lw[0][s] * x[s];
-      b += lw[1][s] * x[s];
-      d += lw[2][s] * x[s];
-    }
-    const size_t o = (size_t)k * g.vs + v;
-    zeta[o] = z;
-    vv[o] = a;
-    vv[plane + o] = b;
-    vv[2 * plane + o] = d;
-  }
-}
-
-// cell: divergence of an edge field (first pass: div vn)
-template <typename R>
-__global__ void __launch_bounds__(256) k_div(DevGrid g, const R* __restrict__ f, R* __restrict__ out, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int c = bx * blockDim.x + threadIdx.x;
-  if (c >= g.nc) return;
-  int ie[3];
-  R kd[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    ie[i] = g.c2e[i * g.cs + c];
-    kd[i] = (R)g.kdiv[i * g.cs + c];
-  }
-  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-  for (int k = k0; k < k1; ++k) {
-    const R* row = f + (size_t)k * g.es;
-    out[(size_t)k * g.cs + c] = kd[0] * row[ie[0]] + kd[1] * row[ie[1]] + kd[2] * row[ie[2]];
-  }
-}
-
-// edge: L1 = grad(div vn) - gradt(curl vn) and the Smagorinsky viscosity
-// from the rhombus deformation of the vertex vectors.
-template <typename R>
-__global__ void __launch_bounds__(256) k_dedge1(DevGrid g, const R* __restrict__ dv, const R* __restrict__ zeta,
-                                                const R* __restrict__ vv, R* __restrict__ l1, R* __restrict__ nu,
-                                                StepCoef cf, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int e = bx * blockDim.x + threadIdx.x;
-  if (e >= g.ne) return;
-  const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
-  int rv[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) rv[i] = g.e2c2v[i * g.es + e];
-  const R invd = (R)g.invd[e], invl = (R)g.invl[e], invlr = (R)g.invlr[e];
-  const R n0 = (R)g.nrm[e], n1 = (R)g.nrm[g.es + e], n2 = (R)g.nrm[2 * g.es + e];
-  const R t0 = (R)g.tan[e], t1 = (R)g.tan[g.es + e], t2 = (R)g.tan[2 * g.es + e];
-  const double ae = g.ae[e];
-  const R smag = (R)(cf.cs * ae);
-  const R cap = (R)(ae / (cf.cap * cf.dt));
-  const size_t plane = (size_t)g.K * g.vs;
-  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-  for (int k = k0; k < k1; ++k) {
-    const R* dr = dv + (size_t)k * g.cs;
-    const R* zr = zeta + (size_t)k * g.vs;
-    l1[(size_t)k * g.es + e] = (dr[c1] - dr[c0]) * invd - (zr[rv[1]] - zr[rv[0]]) * invl;
-    const R* vx = vv + (size_t)k * g.vs;
-    const R* vy = vx + plane;
-    const R* vz = vy + plane;
-    const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
-    const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
-    const R dvn_dt = (tx * n0 + ty * n1 + tz * n2) * invl;
-    const R dvt_dt = (tx * t0 + ty * t1 + tz * t2) * invl;
-    const R dvn_dn = (nx * n0 + ny * n1 + nz * n2) * invlr;
-    const R dvt_dn = (nx * t0 + ny * t1 + nz * t2) * invlr;
-    const R a = dvn_dn - dvt_dt, b = dvt_dn + dvn_dt;
-    const R def = sqrt(a * a + b * b);
-    nu[(size_t)k * g.es + e] = fmin(smag * def, cap);
-  }
-}
-
-// cell + vertex (one launch): div(L1) at cells, curl(L1) at vertices, and the
-// Smagorinsky diffusion of w at cells (reads w_in, writes w_out).
-template <typename R>
-__global__ void __launch_bounds__(256) k_dcv2(DevGrid g, const R* __restrict__ l1, const R* __restrict__ nu,
-                                              const double* __restrict__ w_in, double* __restrict__ w_out,
-                                              R* __restrict__ divl1, R* __restrict__ curll1, int ncb, StepCoef cf,
-                                              int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int K = g.K;
-  if (bx < ncb) {
-    const int c = bx * blockDim.x + threadIdx.x;
-    if (c >= g.nc) return;
-    int ie[3], nb[3];
-    R kd[3];
-    double kl[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      ie[i] = g.c2e[i * g.cs + c];
-      nb[i] = g.c2e2c[i * g.cs + c];
-      kd[i] = (R)g.kdiv[i * g.cs + c];
-      kl[i] = g.klap[i * g.cs + c];
-    }
-    const int k0 = by * kb, k1 = min(K + 1, k0 + kb);
-    for (int k = k0; k < k1; ++k) {
-      if (k < K) {
-        const R* row = l1 + (size_t)k * g.es;
-        divl1[(size_t)k * g.cs + c] = kd[0] * row[ie[0]] + kd[1] * row[ie[1]] + kd[2] * row[ie[2]];
-      }
-      const size_t r = (size_t)k * g.cs + c;
-      double wn = w_in[r];
-      if (cf.diffuse_w && k >= 1 && k <= K - 1) {
-        const R* na = nu + (size_t)(k - 1) * g.es;
-        const R* nbr = nu + (size_t)k * g.es;
-        R nuc = R(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) nuc += R(0.5) * (na[ie[i]] + nbr[ie[i]]);
-        nuc = nuc / R(3);
-        const double* wr = w_in + (size_t)k * g.cs;
-        double lw = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) lw += kl[i] * (wr[nb[i]] - wn);
-        wn = wn + cf.dt * (double)nuc * lw;
-      }
-      w_out[r] = wn;
-    }
-  } else {
-    const int v = (bx - ncb) * blockDim.x + threadIdx.x;
-    if (v >= g.nv) return;
-    int idx[6];
-    R cc[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      idx[s] = g.v2e[s * g.vs + v];
-      cc[s] = (R)g.kcurl[s * g.vs + v];
-    }
-    const int k0 = by * kb, k1 = min(K, k0 + kb);
-    for (int k = k0; k < k1; ++k) {
-      const R* row = l1 + (size_t)k * g.es;
-      R z = cc[0] * row[idx[0]];
-#pragma unroll
-      for (int s = 1; s < 6; ++s) z += cc[s] * row[idx[s]];
-      curll1[(size_t)k * g.vs + v] = z;
-    }
-  }
-}
-
-// edge: L2 = lapv(L1) and vn += dt nu L1 - k4 A_e^2 L2 (in place).
-template <typename R>
-__global__ void __launch_bounds__(256) k_dedge2(DevGrid g, R* __restrict__ vn, const R* __restrict__ l1,
-                                                const R* __restrict__ nu, const R* __restrict__ divl1,
-                                                const R* __restrict__ curll1, StepCoef cf, int kb) {
-  int bx, by;
-  tile_coords(bx, by);
-  const int e = bx * blockDim.x + threadIdx.x;
-  if (e >= g.ne) return;
-  const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
-  const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
-  const R invd = (R)g.invd[e], invl = (R)g.invl[e];
-  const double ae = g.ae[e];
-  const R k4a2 = (R)(cf.k4 * ae * ae);
-  const R dt = (R)cf.dt;
-  const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-  for (int k = k0; k < k1; ++k) {
-    const R* dr = divl1 + (size_t)k * g.cs;
-    const R* zr = curll1 + (size_t)k * g.vs;
-    const R l2 = (dr[c1] - dr[c0]) * invd - (zr[v1] - zr[v0]) * invl;
-    const size_t r = (size_t)k * g.es + e;
-    vn[r] = vn[r] + dt * nu[r] * l1[r] - k4a2 * l2;
-  }
-}
+using bodies::vt_row;
 
 // ---------------------------------------------------------------------------
 // conservation diagnostics: fixed-order block partials, then one block
@@ -822,89 +120,67 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
   }
 }
 
-inline dim3 grid2(int n, int levels, const Tile& t) {
-  const int nbx = (n + t.threads - 1) / t.threads;
-  const int nby = (levels + t.kb - 1) / t.kb;
-  return dim3(nbx, nby);
-}
-
 }  // namespace
-
-// Column chunking: at most 8 waves (chunks) per block of 64 columns, chunk
-// length LM in {8, 12, 16} (the smallest that fits); chunks hold >= 2 rows
-// whenever there is more than one.  Supports n_lev <= 129.
-int col_chunks(int K, int* lm) {
-  const int nrow = std::max(K - 1, 0);
-  *lm = nrow <= 64 ? 8 : (nrow <= 96 ? 12 : 16);
-  return std::max(1, (nrow + *lm - 1) / *lm);
-}
-
-template <typename R, bool CORR>
-void launch_col(const DevGrid& g, const ColArgs<R>& a, const StepCoef& c, hipStream_t s) {
-  int lm;
-  const int P = col_chunks(g.K, &lm);
-  const int nblk = (g.nc + 63) / 64;
-  const size_t smem = P > 1 ? 6 * sizeof(double) * 64 * (size_t)P : 0;
-  if (lm == 8)
-    k_colq<R, CORR, 8><<<nblk, 64 * P, smem, s>>>(g, a, c, P);
-  else if (lm == 12)
-    k_colq<R, CORR, 12><<<nblk, 64 * P, smem, s>>>(g, a, c, P);
-  else
-    k_colq<R, CORR, 16><<<nblk, 64 * P, smem, s>>>(g, a, c, P);
-}
 
 const char* const kKernelNames[K_COUNT] = {
     "vort_ke_pred", "edge_pred", "column_pred",
     "vort_ke_corr", "edge_corr", "column_corr",
     "diff_vertex", "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2"};
 
-#define LAUNCH(id, ...)                     \
-  do {                                      \
-    if (prof) prof->mark(s, id);            \
-    __VA_ARGS__;                            \
-    if (prof) prof->mark(s, -1);            \
-  } while (0)
+int col_chunks(int K, int* lm) { return bodies::col_chunks_lm(K, lm); }
 
 int diag_partial_count(const DevGrid& g) {
   return (g.nc + kDiagThreads - 1) / kDiagThreads + (g.ne + kDiagThreads - 1) / kDiagThreads;
 }
 
+namespace {
+
+template <typename B>
+void one(int id, const DevGrid& g, const typename B::Args& a, const Tile* T, hipStream_t s, Prof* prof) {
+  const bodies::Geom geo = bodies::geom_of(id, g, T);
+  if (prof) prof->mark(s, id);
+  bodies::k_one<B><<<dim3(geo.nbx, geo.nby), geo.threads, geo.smem, s>>>(g, a);
+  if (prof) prof->mark(s, -1);
+}
+
+template <typename R, bool CORR>
+void one_col(int id, const DevGrid& g, const bodies::ColPhaseArgs<R>& a, const Tile* T, hipStream_t s, Prof* prof) {
+  int lm;
+  bodies::col_chunks_lm(g.K, &lm);
+  if (lm == 8)
+    one<bodies::BCol<R, CORR, 8>>(id, g, a, T, s, prof);
+  else if (lm == 12)
+    one<bodies::BCol<R, CORR, 12>>(id, g, a, T, s, prof);
+  else
+    one<bodies::BCol<R, CORR, 16>>(id, g, a, T, s, prof);
+}
+
+}  // namespace
+
 template <typename R>
 void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* T, hipStream_t s, Prof* prof) {
-  const int K = g.K;
+  using namespace bodies;
+  const SubstepArgs<R> a = substep_args<R>(g, b, c, T);
   // predictor: advective tendencies at the substep start, momentum, column
-  const Tile& tv = T[T_VC];
-  const int ncb = (g.nc + tv.threads - 1) / tv.threads;
-  const dim3 gvc(ncb + (g.nv + tv.threads - 1) / tv.threads, (K + tv.kb - 1) / tv.kb);
-  LAUNCH(K_VC_P, k_vc<R, false><<<gvc, tv.threads, 0, s>>>(g, b.vn, b.zeta, b.kc, nullptr, ncb, tv.kb));
-  LAUNCH(K_EDGE_P, k_edge<R, false><<<grid2(g.ne, K, T[T_EDGE]), T[T_EDGE].threads, 0, s>>>(
-                       g, b.vn, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, c, T[T_EDGE].kb));
-  ColArgs<R> ca{b.w, b.rho, b.ex, b.th, b.vn, b.vns, nullptr, nullptr, b.ws, nullptr, nullptr, nullptr};
-  LAUNCH(K_COL_P, launch_col<R, false>(g, ca, c, s));
+  one<BVc<R, false>>(K_VC_P, g, a.vc_p, T, s, prof);
+  one<BEdge<R, false>>(K_EDGE_P, g, a.e_p, T, s, prof);
+  one_col<R, false>(K_COL_P, g, a.c_p, T, s, prof);
   // corrector: tendencies at the predicted state, damping, momentum, column
-  LAUNCH(K_VC_C, k_vc<R, true><<<gvc, tv.threads, 0, s>>>(g, b.vns, b.zeta, b.kc, b.d2, ncb, tv.kb));
-  LAUNCH(K_EDGE_C, k_edge<R, true><<<grid2(g.ne, K, T[T_EDGE]), T[T_EDGE].threads, 0, s>>>(
-                       g, b.vns, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, c, T[T_EDGE].kb));
-  ColArgs<R> cc{b.w, b.rho, b.ex, b.th, b.vn, b.vn_out, b.vns, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out};
-  LAUNCH(K_COL_C, launch_col<R, true>(g, cc, c, s));
+  one<BVc<R, true>>(K_VC_C, g, a.vc_c, T, s, prof);
+  one<BEdge<R, true>>(K_EDGE_C, g, a.e_c, T, s, prof);
+  one_col<R, true>(K_COL_C, g, a.c_c, T, s, prof);
 }
 
 template <typename R>
 void launch_diffusion(const DevGrid& g, R* vn, const double* w_in, double* w_out, R* l1, R* nu, R* dv, R* dl1,
                       R* zeta, R* vv, const StepCoef& c, const Tile* T, hipStream_t s, Prof* prof) {
-  const int K = g.K;
-  LAUNCH(K_DVERT, k_dvert<R><<<grid2(g.nv, K, T[T_DVERT]), T[T_DVERT].threads, 0, s>>>(g, vn, vv, zeta, T[T_DVERT].kb));
-  LAUNCH(K_DDIV, k_div<R><<<grid2(g.nc, K, T[T_DCELL]), T[T_DCELL].threads, 0, s>>>(g, vn, dv, T[T_DCELL].kb));
-  LAUNCH(K_DEDGE1, k_dedge1<R><<<grid2(g.ne, K, T[T_DEDGE]), T[T_DEDGE].threads, 0, s>>>(g, dv, zeta, vv, l1, nu, c,
-                                                                                         T[T_DEDGE].kb));
-  // cells (K+1 half levels for w) and vertices share one launch
-  const Tile& t = T[T_DCELL];
-  const int ncb = (g.nc + t.threads - 1) / t.threads;
-  const int nvb = (g.nv + t.threads - 1) / t.threads;
-  const dim3 gr(ncb + nvb, (K + 1 + t.kb - 1) / t.kb);
-  LAUNCH(K_DCV2, k_dcv2<R><<<gr, t.threads, 0, s>>>(g, l1, nu, w_in, w_out, dl1, zeta, ncb, c, t.kb));
-  LAUNCH(K_DEDGE2, k_dedge2<R><<<grid2(g.ne, K, T[T_DEDGE]), T[T_DEDGE].threads, 0, s>>>(g, vn, l1, nu, dl1, zeta, c,
-                                                                                         T[T_DEDGE].kb));
+  using namespace bodies;
+  const DiffusionArgs<R> d = diffusion_args<R>(g, vn, w_in, w_out, l1, nu, dv, dl1, zeta, vv, c, T);
+  one<BDvert<R>>(K_DVERT, g, d.dv, T, s, prof);
+  one<BDiv<R>>(K_DDIV, g, d.dd, T, s, prof);
+  one<BDedge1<R>>(K_DEDGE1, g, d.d1, T, s, prof);
+  one<BDcv2<R>>(K_DCV2, g, d.cv, T, s, prof);  // cells (K+1 half levels) and vertices in one launch
+  one<BDedge2<R>>(K_DEDGE2, g, d.d2, T, s, prof);
 }
 
 template <typename R>

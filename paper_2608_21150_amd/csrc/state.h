@@ -1,0 +1,113 @@
+// Internal definitions of the grid and state handles (shared by the C-ABI
+// implementation files; not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <vector>
+
+#include "dycore.h"
+#include "internal.h"
+#include "kernels.h"
+
+struct dc_grid {
+  using HostGrid = dc::HostGrid;
+  using DevGrid = dc::DevGrid;
+  HostGrid h;
+  DevGrid d{};
+  bool uploaded = false;
+  int device = -1;
+  std::vector<void*> allocs;
+  std::atomic<int> states{0};
+};
+
+struct dc_state {
+  using DevGrid = dc::DevGrid;
+  using Tile = dc::Tile;
+  using Prof = dc::Prof;
+  static constexpr int kTiles = dc::T_COUNT;
+  dc_grid* grid = nullptr;
+  dc_params p{};
+  dc_precision prec = DC_PREC_FP64;
+  dc_diffusion diff = DC_DIFF_PLAIN;
+  dc_fields buf[2]{};
+  int cur = 0;
+  hipStream_t stream = nullptr;
+  DevGrid d{};  // grid view plus per-state Coriolis and sponge tables
+  Tile tiles[kTiles];
+  Prof prof;
+  // workspace carve-up
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
+  double *wstar, *wtmp, *fe, *tau, *diag_part, *diag_out;
+};
+
+
+namespace dc {
+
+inline StepCoef make_coef(const dc_state* s, double dt, int nsub) {
+  StepCoef c{};
+  c.dtau = dt / nsub;
+  c.dt = dt;
+  c.eta = s->p.eta;
+  c.a0 = s->p.adv_w0;
+  c.a1 = s->p.adv_w1;
+  c.cpd = s->p.cpd;
+  c.rd_cvd = s->p.rd / s->p.cvd;
+  c.cvd_rd = s->p.cvd / s->p.rd;
+  c.c4a2 = s->p.divdamp_c4 * s->grid->h.mean_area * s->grid->h.mean_area;
+  c.cs = s->p.smag_cs;
+  c.cap = s->p.smag_cap;
+  c.k4 = s->p.hdiff_k4;
+  c.diffuse_w = s->p.diffuse_w;
+  return c;
+}
+
+// Buffers of substep i of a step that starts in buffer set `cur`; the last
+// substep writes w to the diffusion staging field when diffusion follows.
+template <typename R>
+Bufs<R> substep_bufs(const dc_state* s, int cur_idx, bool w_to_staging) {
+  const dc_fields& cur = s->buf[cur_idx];
+  const dc_fields& nxt = s->buf[1 - cur_idx];
+  Bufs<R> b{};
+  b.vn = static_cast<const R*>(cur.vn);
+  b.w = static_cast<const double*>(cur.w);
+  b.rho = static_cast<const double*>(cur.rho);
+  b.ex = static_cast<const double*>(cur.exner);
+  b.th = static_cast<const double*>(cur.theta_v);
+  b.vt = static_cast<R*>(s->vt);
+  b.tvn0 = static_cast<R*>(s->tvn0);
+  b.vns = static_cast<R*>(s->vns);
+  b.kc = static_cast<R*>(s->kc);
+  b.d2 = static_cast<R*>(s->d2);
+  b.zeta = static_cast<R*>(s->zeta);
+  b.vv = static_cast<R*>(s->vv);
+  b.ws = s->wstar;
+  b.wtmp = s->wtmp;
+  b.vn_out = static_cast<R*>(nxt.vn);
+  b.w_out = w_to_staging ? s->wtmp : static_cast<double*>(nxt.w);
+  b.rho_out = static_cast<double*>(nxt.rho);
+  b.ex_out = static_cast<double*>(nxt.exner);
+  b.th_out = static_cast<double*>(nxt.theta_v);
+  return b;
+}
+
+// Default launch tiles: levels per block so that each launch has a few
+// thousand blocks when the grid is large, one level per block on small grids.
+inline void default_tiles(const HostGrid& h, Tile* t) {
+  auto kb_for = [&](int n, int levels) {
+    const int nbx = (n + 255) / 256;
+    int kb = (int)((long long)levels * nbx / 2048);
+    return std::max(1, std::min(kb, 16));
+  };
+  t[T_VC] = {256, kb_for(h.nc + h.nv, h.K)};
+  t[T_EDGE] = {256, kb_for(h.ne, h.K)};
+  t[T_DVERT] = {256, kb_for(h.nv, h.K)};
+  t[T_DCELL] = {256, kb_for(h.nc + h.nv, h.K + 1)};
+  t[T_DEDGE] = {256, kb_for(h.ne, h.K)};
+}
+
+}  // namespace dc

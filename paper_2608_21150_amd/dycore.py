@@ -94,6 +94,9 @@ def _load():
         "dc_ensemble_create": (ctypes.c_int, [ctypes.POINTER(_p), ctypes.c_int32, ctypes.POINTER(_p)]),
         "dc_ensemble_step": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
         "dc_ensemble_destroy": (ctypes.c_int, [_p]),
+        "dc_ensemble_step_eager": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
+        "dc_ensemble_autotune": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32, ctypes.c_char_p]),
+        "dc_ensemble_schedule": (ctypes.c_int, [_p, ctypes.c_char_p, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -262,6 +265,41 @@ class State:
     def close(self):
         if self.handle:
             check(lib.dc_state_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Members stepped together by one graph launch per step (batched kernels)."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        arr = (_p * len(self.members))(*[m.handle for m in self.members])
+        h = _p()
+        check(lib.dc_ensemble_create(arr, len(self.members), ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, dt: float, nsub: int, eager: bool = False):
+        fn = lib.dc_ensemble_step_eager if eager else lib.dc_ensemble_step
+        check(fn(self.handle, float(dt), int(nsub)))
+
+    def autotune(self, dt: float, nsub: int, cache_path: str | None = None):
+        check(lib.dc_ensemble_autotune(self.handle, float(dt), int(nsub),
+                                       cache_path.encode() if cache_path else None))
+
+    def schedule(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        check(lib.dc_ensemble_schedule(self.handle, buf, 512))
+        return buf.value.decode()
+
+    def close(self):
+        if self.handle:
+            check(lib.dc_ensemble_destroy(self.handle))
             self.handle = None
 
     def __del__(self):

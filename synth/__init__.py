@@ -5,4 +5,4 @@ time step's arithmetic.
 """
 from .grid import make_grid, expected_counts, EARTH_RADIUS
 from .state import initial_state, vertical, reference
-from .workloads import WORKLOADS, build_workload
+from .workloads import WORKLOADS, build_workload, ensemble_member
