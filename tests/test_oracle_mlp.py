@@ -1,0 +1,91 @@
+"""Pins of the oracle surrogate MLP (CPU): gradients against central finite
+differences, GELU against its closed form and derivative, Adam against a
+hand-worked first step, features against their definitions on a grid."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+
+def test_gelu_values_and_derivative():
+    x = np.array([-3.0, -1.0, 0.0, 0.5, 2.0])
+    want = [v * 0.5 * (1 + math.erf(v / math.sqrt(2))) for v in x]
+    assert np.allclose(M.gelu(x), want, rtol=0, atol=1e-15)
+    h = 1e-6
+    fd = (M.gelu(x + h) - M.gelu(x - h)) / (2 * h)
+    assert np.allclose(M.gelu_grad(x), fd, rtol=0, atol=1e-9)
+    assert M.gelu(np.array([0.0]))[0] == 0.0 and abs(M.gelu_grad(np.array([0.0]))[0] - 0.5) < 1e-15
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(0)
+    p = M.init_params(1)
+    x = rng.normal(size=(7, 18))
+    t = rng.normal(size=7)
+    _, g = M.loss_and_grads(p, x, t)
+    h = 1e-6
+    worst = 0.0
+    for k in p:
+        flat = p[k].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = M.loss_and_grads(p, x, t)
+            flat[idx] = old - h
+            lm, _ = M.loss_and_grads(p, x, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[k].reshape(-1)[idx]
+            worst = max(worst, abs(fd - an) / max(1e-3, abs(fd)))
+    assert worst < 1e-6
+
+
+def test_adam_first_step_is_signed_lr():
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -0.25, 0.0])}
+    m = {"w": np.zeros(3)}
+    v = {"w": np.zeros(3)}
+    M.adam_step(p, g, m, v, 1, lr=0.1)
+    # first bias-corrected step: lr * g / (|g| + eps)
+    assert np.allclose(p["w"], [1.0 - 0.1, -2.0 + 0.1, 3.0], atol=1e-7)
+
+
+def test_cosine_schedule_end_points():
+    assert M.cosine_lr(0, 100) == pytest.approx(1e-3)
+    assert M.cosine_lr(100, 100) == pytest.approx(1e-5)
+    assert M.cosine_lr(50, 100) == pytest.approx(0.5 * (1e-3 + 1e-5))
+
+
+def test_init_is_kaiming_uniform_and_seeded():
+    a, b = M.init_params(3), M.init_params(3)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+    assert np.max(np.abs(a["w1"])) <= math.sqrt(6 / 18)
+    assert np.max(np.abs(a["w2"])) <= math.sqrt(6 / 64)
+    assert np.all(a["b1"] == 0)
+
+
+def test_features_definitions():
+    from oracle.grid import Grid
+    from synth import initial_state, make_grid
+    from oracle import operators as op
+
+    g0 = make_grid(2, 1)
+    S, vert = initial_state(g0, 3, 10e3, seed=2, vn_sigma=1.0)
+    g = Grid(g0, vert)
+    f = M.features(g, S["vn"])
+    e, k = 17, 1
+    vt = op.recon_vt(g, S["vn"])
+    assert f[k, e, 0] == S["vn"][k, e] and f[k, e, 1] == vt[k, e]
+    assert f[k, e, 3] == S["vn"][k, g.e2c2e[e, 1]]
+    D = op.div(g, S["vn"])
+    assert f[k, e, 11] == D[k, g.e2c[e, 1]]
+    z = op.curl(g, S["vn"])
+    assert f[k, e, 14] == z[k, g.e2c2v[e, 2]]
+    assert np.allclose(f[0, :, 16].mean(), 1.0) and np.allclose(f[0, :, 17].mean(), 1.0)
+    # odd in the flow: flipping vn flips the 16 flow features, keeps geometry
+    f2 = M.features(g, -S["vn"])
+    assert np.allclose(f2[..., :16], -f[..., :16], rtol=0, atol=1e-12)
+    assert np.array_equal(f2[..., 16:], f[..., 16:])
