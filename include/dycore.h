@@ -39,6 +39,7 @@ extern "C" {
 typedef struct dc_grid dc_grid;
 typedef struct dc_state dc_state;
 typedef struct dc_ensemble dc_ensemble;
+typedef struct dc_mlp dc_mlp;
 
 typedef enum {
   DC_OK = 0,
@@ -142,6 +143,8 @@ typedef struct {
   double theta_mass;  /* sum_c A_c sum_j rho theta_v dz_j         [kg K] */
   double max_abs_w, max_abs_vn;
   int64_t n_nonfinite; /* NaN/Inf entries over the five fields           */
+  double fallback_fraction; /* surrogate mode: share of edge columns that ran
+                               the plain diffusion in the last non-judge step */
 } dc_diag;
 
 /* Validate the description, derive canonical tables, orientation and
@@ -225,6 +228,97 @@ dc_status dc_ensemble_autotune(dc_ensemble *ens, double dt, int32_t nsubsteps, c
  * blocks per CU of every phase, 0 = one block per tile). */
 dc_status dc_ensemble_schedule(const dc_ensemble *ens, char *buf, size_t n);
 dc_status dc_ensemble_destroy(dc_ensemble *ens);
+
+/*
+ * Learned diffusion surrogate (DC_DIFF_SURROGATE).  The paper motivates a
+ * dynamical core that couples to machine-learning workflows (Sections 3
+ * and 6); the network is this library's reading: per (edge, level) an
+ * 18 -> 64 -> 64 -> 1 perceptron with exact (erf) GELU, BF16 operands on the
+ * matrix cores and FP32 accumulation, predicting T = (vn after the vn
+ * diffusion - vn before) / dt from 18 stencil features, in this order:
+ *   vn_e, vt_e, vn of the 4 e2c2e edges, vt of the 4 e2c2e edges,
+ *   div vn at e2c[0], e2c[1], curl vn at the 4 e2c2v vertices,
+ *   l_e / mean(l), d_e / mean(d).
+ * Parameters (DC_MLP_NPARAMS floats, row-major): W1 [18][64], b1 [64],
+ * W2 [64][64], b2 [64], w3 [64], b3 [1]; y = W3 gelu(W2 gelu(W1 x' + b1) + b2)
+ * + b3 with x' = (x - mean) / std, and T = y * target_std.
+ * Surrogate step: every judge_every-th step (the first included) runs the
+ * plain diffusion, keeps its viscosity for w, and flags every edge column
+ * whose residual dt |T_mlp - T_plain|_2 / max(|vn|_2, sqrt(K) m/s) exceeds
+ * the threshold (flags hold until the next judge step).  The other steps
+ * add dt T_mlp to vn except on flagged columns and on columns with a
+ * feature outside the normalisation range, which run the plain vn
+ * diffusion (and refresh their viscosity); w is diffused with the held
+ * viscosity.  An MLP must outlive the states it is set on.
+ */
+#define DC_MLP_NFEATURES 18
+#define DC_MLP_NPARAMS 5441
+
+typedef struct {
+  int32_t batch;   /* samples per Adam step, a multiple of 128 (4096)      */
+  int32_t epochs;  /* passes over the set (2)                              */
+  double lr0, lr1; /* cosine decay from lr0 to lr1 over all steps (1e-3, 1e-5) */
+  uint64_t seed;   /* epoch shuffles                                       */
+  int32_t shuffle; /* 1: permute the set every epoch                       */
+  int32_t augment; /* 1: flip the sign of the 16 flow features and the
+                      target of a hashed half of the samples (the diffusion
+                      is odd in vn)                                        */
+} dc_train_cfg;
+
+typedef struct {
+  int64_t steps, judge_steps; /* surrogate steps since dc_state_set_mlp, judge steps among them */
+  int64_t judge_flagged;      /* columns flagged by the last judge step                        */
+  int64_t range_flagged;      /* columns with out-of-range features in the last non-judge step  */
+  int64_t fallback;           /* columns that ran the plain diffusion in that step              */
+  int64_t n_columns;          /* edge columns of the grid                                        */
+} dc_surrogate_info;
+
+/* Seeded Kaiming-uniform weights (fan-in, gain sqrt 2), zero biases, identity
+ * normalisation with an unbounded range, on the current device. */
+dc_status dc_mlp_create(uint64_t seed, dc_mlp **out);
+dc_status dc_mlp_destroy(dc_mlp *mlp);
+/* Host copies of the parameters (n must be DC_MLP_NPARAMS); set resets Adam. */
+dc_status dc_mlp_get_params(dc_mlp *mlp, float *host, int64_t n);
+dc_status dc_mlp_set_params(dc_mlp *mlp, const float *host, int64_t n);
+/* Normalisation: per-feature mean, std (> 0), range [min, max] and the
+ * target scale.  get fills 73 floats: mean[18], std[18], min[18], max[18], tstd. */
+dc_status dc_mlp_set_norm(dc_mlp *mlp, const float *mean, const float *std_, const float *fmin,
+                          const float *fmax, float target_std);
+dc_status dc_mlp_get_norm(const dc_mlp *mlp, float *host, int64_t n);
+/* Training sets live in device memory, row-major [19][stride] float:
+ * rows 0..17 the features, row 18 the target T, samples 0..n-1 used.
+ * fit_norm sets the normalisation from the set (synchronising): the 16 flow
+ * features and the target get mean 0 and their root mean square as scale
+ * with the symmetric range [-max|x|, max|x|] (the set under sign
+ * augmentation); the two length ratios get mean, standard deviation and
+ * [min, max].  DC_ENONFINITE if the set holds NaN/Inf. */
+dc_status dc_mlp_fit_norm(dc_mlp *mlp, const float *dev_buf, int64_t stride, int64_t n);
+/* MSE in normalised units, Adam (0.9, 0.999, 1e-8), synchronising; the
+ * per-step mean batch loss is kept for dc_mlp_loss_trace.  The set's
+ * floor(n / batch) * batch first positions of every epoch order are used. */
+dc_status dc_mlp_train(dc_mlp *mlp, const float *dev_buf, int64_t stride, int64_t n, const dc_train_cfg *cfg);
+dc_status dc_mlp_loss_trace(const dc_mlp *mlp, float *host, int64_t cap, int64_t *n_out);
+/* Synchronising host-to-host evaluation: host_x [n][18] raw features ->
+ * host_y [n] = T.  (Testing and offline evaluation.) */
+dc_status dc_mlp_forward(dc_mlp *mlp, const float *host_x, int64_t n, float *host_y);
+/* Gradient of mean((y - t / target_std)^2) over n rows (n a multiple of
+ * 128, no augmentation) with respect to every parameter; loss may be NULL. */
+dc_status dc_mlp_grad(dc_mlp *mlp, const float *host_x, const float *host_t, int64_t n, float *host_grad,
+                      float *loss);
+/* Attach an MLP to a DC_DIFF_SURROGATE state (restarts the judge cycle).
+ * DC_ESTATE for other modes; dc_dycore_step on a surrogate state without an
+ * MLP returns DC_ESTATE. */
+dc_status dc_state_set_mlp(dc_state *st, const dc_mlp *mlp, double resid_threshold, int32_t judge_every);
+dc_status dc_surrogate_stats(dc_state *st, dc_surrogate_info *out);
+/* One plain step of a DC_DIFF_SURROGATE state (nsubsteps >= 0; 0 = the
+ * diffusion alone) that records n_samples training pairs: features of the
+ * state before the diffusion and T, at (edge, level) points drawn without
+ * replacement by a seeded Feistel permutation, into columns
+ * offset .. offset + n_samples - 1 of dev_buf ([19][stride], see above).
+ * host_index (may be NULL) receives k * n_edges + e of every sample in the
+ * caller's numbering (synchronising). */
+dc_status dc_surrogate_collect(dc_state *st, double dt, int32_t nsubsteps, uint64_t seed, int64_t n_samples,
+                               float *dev_buf, int64_t stride, int64_t offset, int64_t *host_index);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *dc_last_error(void);

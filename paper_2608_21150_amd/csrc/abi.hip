@@ -46,10 +46,12 @@ dc_status fail(dc_status code, const std::string& msg) {
 size_t elem_size(dc_precision prec) { return prec == DC_PREC_MIXED ? sizeof(float) : sizeof(double); }
 
 struct Layout {
-  size_t vt, tvn0, vns, kc, d2, zeta, vv, wstar, wtmp, fe, tau, dpart, dout, total;
+  size_t vt, tvn0, vns, kc, d2, zeta, vv, wstar, wtmp, fe, tau, dpart, dout;
+  size_t s_tmlp, s_nu, s_fj, s_fr, s_cnt;  // surrogate mode only
+  size_t total;
 };
 
-Layout workspace_layout(const HostGrid& h, dc_precision prec) {
+Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff) {
   const size_t r = elem_size(prec);
   const size_t K = h.K, K1 = h.K + 1;
   size_t off = 0;
@@ -73,6 +75,14 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec) {
   const int nblk = (h.nc + 255) / 256 + (h.ne + 255) / 256;
   L.dpart = take(5 * (size_t)nblk * 8);
   L.dout = take(8 * 8);
+  L.s_tmlp = L.s_nu = L.s_fj = L.s_fr = L.s_cnt = 0;
+  if (diff == DC_DIFF_SURROGATE) {
+    L.s_tmlp = take(K * h.es * r);
+    L.s_nu = take(K * h.es * r);
+    L.s_fj = take((size_t)h.es * 4);
+    L.s_fr = take((size_t)h.es * 4);
+    L.s_cnt = take(4 * 4);
+  }
   L.total = off;
   return L;
 }
@@ -161,12 +171,10 @@ template <typename R>
 void enqueue_step(dc_state* s, double dt, int nsub) {
   const StepCoef c = make_coef(s, dt, nsub);
   const bool diffuse = s->diff != DC_DIFF_NONE;
-  for (int i = 0; i < nsub; ++i) {
-    const Bufs<R> b = substep_bufs<R>(s, s->cur, i == nsub - 1 && diffuse);
-    launch_substep<R>(s->d, b, c, s->tiles, s->stream, &s->prof);
-    s->cur ^= 1;
-  }
-  if (diffuse) {
+  enqueue_substeps<R>(s, c, nsub, diffuse);
+  if (s->diff == DC_DIFF_SURROGATE) {
+    surrogate_diffusion<R>(s, c);
+  } else if (diffuse) {
     const dc_fields& cur = s->buf[s->cur];
     launch_diffusion<R>(s->d, static_cast<R*>(cur.vn), s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt),
                         static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
@@ -188,6 +196,12 @@ dc_status run_diag(dc_state* s, dc_diag* out) {
   double h[5];
   DC_TRY(hipMemcpyAsync(h, s->diag_out, sizeof(h), hipMemcpyDeviceToHost, s->stream));
   DC_TRY(hipStreamSynchronize(s->stream));
+  out->fallback_fraction = 0.0;
+  if (s->diff == DC_DIFF_SURROGATE) {
+    int cnt[3];
+    DC_TRY(hipMemcpy(cnt, s->sur_cnt, sizeof(cnt), hipMemcpyDeviceToHost));
+    out->fallback_fraction = (double)cnt[2] / s->grid->h.ne;
+  }
   out->mass = h[0];
   out->theta_mass = h[1];
   out->max_abs_w = h[2];
@@ -300,8 +314,9 @@ dc_status dc_field_bytes(const dc_grid* g, dc_precision prec, int32_t field, siz
 dc_status dc_state_workspace_bytes(const dc_grid* g, dc_precision prec, dc_diffusion diff, size_t* bytes) {
   if (!g || !bytes) return fail(DC_EINVAL, "NULL argument");
   if (prec != DC_PREC_FP64 && prec != DC_PREC_MIXED) return fail(DC_EINVAL, "bad precision");
-  if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE) return fail(DC_EINVAL, "unsupported diffusion mode");
-  *bytes = workspace_layout(g->h, prec).total;
+  if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE && diff != DC_DIFF_SURROGATE)
+    return fail(DC_EINVAL, "bad diffusion mode");
+  *bytes = workspace_layout(g->h, prec, diff).total;
   return DC_OK;
 }
 
@@ -311,12 +326,13 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   *out = nullptr;
   dc_grid* g = const_cast<dc_grid*>(gc);
   if (prec != DC_PREC_FP64 && prec != DC_PREC_MIXED) return fail(DC_EINVAL, "bad precision");
-  if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE) return fail(DC_EINVAL, "unsupported diffusion mode");
+  if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE && diff != DC_DIFF_SURROGATE)
+    return fail(DC_EINVAL, "bad diffusion mode");
   const dc_fields* bs[2] = {&a, &b};
   for (int i = 0; i < 2; ++i)
     for (int f = 0; f < DC_FIELD_COUNT; ++f)
       if (!aligned(field_ptr(*bs[i], f))) return fail(DC_EINVAL, "field buffers must be non-NULL and 256-byte aligned");
-  const Layout L = workspace_layout(g->h, prec);
+  const Layout L = workspace_layout(g->h, prec, diff);
   if (!aligned(workspace)) return fail(DC_EINVAL, "workspace must be non-NULL and 256-byte aligned");
   if (ws_bytes < L.total) return fail(DC_EINVAL, "workspace too small: need " + std::to_string(L.total) + " bytes");
   const dc_params& p = *params;
@@ -355,6 +371,14 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->tau = reinterpret_cast<double*>(w + L.tau);
   s->diag_part = reinterpret_cast<double*>(w + L.dpart);
   s->diag_out = reinterpret_cast<double*>(w + L.dout);
+  if (diff == DC_DIFF_SURROGATE) {
+    s->sur_tmlp = w + L.s_tmlp;
+    s->sur_nu = w + L.s_nu;
+    s->sur_fj = reinterpret_cast<int*>(w + L.s_fj);
+    s->sur_fr = reinterpret_cast<int*>(w + L.s_fr);
+    s->sur_cnt = reinterpret_cast<int*>(w + L.s_cnt);
+    surrogate_geometry(s);
+  }
   // per-state tables: Coriolis parameter and sponge profile
   const HostGrid& h = g->h;
   std::vector<double> fe(h.es, 0.0), tau(h.K + 1, 0.0);
@@ -369,6 +393,10 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   }
   hipError_t e1 = hipMemcpy(s->fe, fe.data(), fe.size() * 8, hipMemcpyHostToDevice);
   hipError_t e2 = hipMemcpy(s->tau, tau.data(), tau.size() * 8, hipMemcpyHostToDevice);
+  if (e1 == hipSuccess && e2 == hipSuccess && diff == DC_DIFF_SURROGATE) {
+    // flags and counters start cleared (the first surrogate step judges)
+    e1 = hipMemset(w + L.s_fj, 0, L.s_cnt + 16 - L.s_fj);
+  }
   if (e1 != hipSuccess || e2 != hipSuccess) {
     delete s;
     return fail(DC_EHIP, std::string("hipMemcpy(state tables): ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
@@ -450,6 +478,7 @@ dc_status dc_dycore_step(dc_state* s, double dt, int32_t nsub) {
   if (!s) return fail(DC_EINVAL, "state is NULL");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DC_EINVAL, "dt must be finite and > 0");
   if (nsub < 1 || nsub > 1000) return fail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
+  if (s->diff == DC_DIFF_SURROGATE && !s->sur) return fail(DC_ESTATE, "surrogate mode needs dc_state_set_mlp first");
   if (s->prec == DC_PREC_MIXED)
     enqueue_step<float>(s, dt, nsub);
   else
@@ -504,6 +533,7 @@ dc_status dc_state_destroy(dc_state* s) {
   hipError_t e = hipStreamSynchronize(s->stream);
   for (hipEvent_t ev : s->prof.ev) (void)hipEventDestroy(ev);
   s->grid->states.fetch_sub(1);
+  surrogate_free(s);
   delete s;
   if (e != hipSuccess) return fail(DC_EHIP, std::string("pending work failed: ") + hipGetErrorString(e));
   return DC_OK;

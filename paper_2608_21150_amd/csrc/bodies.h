@@ -581,6 +581,93 @@ struct BCol {
 // diffusion
 // ---------------------------------------------------------------------------
 // vertex: least-squares vertex vector V_v (3 components) and vorticity.
+// ---------------------------------------------------------------------------
+// diffusion arithmetic shared by the plain kernels and the per-column
+// fallback of the surrogate (identical expressions, identical results)
+// ---------------------------------------------------------------------------
+// first vector Laplacian at edge e: grad(div vn) - gradt(curl vn)
+template <typename R>
+__device__ __forceinline__ R dif_l1(const DevGrid& g, const R* dr, const R* zr, int e) {
+  const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
+  const int v0 = g.e2c2v[e], v1 = g.e2c2v[g.es + e];
+  const R invd = (R)g.invd[e], invl = (R)g.invl[e];
+  return (dr[c1] - dr[c0]) * invd - (zr[v1] - zr[v0]) * invl;
+}
+// Smagorinsky viscosity at edge e from the rhombus deformation of the vertex
+// vectors (vx, vy, vz: the three components at one level)
+template <typename R>
+__device__ __forceinline__ R dif_nu(const DevGrid& g, const R* vx, const R* vy, const R* vz, int e,
+                                    const StepCoef& cf) {
+  int rv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) rv[i] = g.e2c2v[i * g.es + e];
+  const R invl = (R)g.invl[e], invlr = (R)g.invlr[e];
+  const R n0 = (R)g.nrm[e], n1 = (R)g.nrm[g.es + e], n2 = (R)g.nrm[2 * g.es + e];
+  const R t0 = (R)g.tan[e], t1 = (R)g.tan[g.es + e], t2 = (R)g.tan[2 * g.es + e];
+  const double ae = g.ae[e];
+  const R smag = (R)(cf.cs * ae);
+  const R cap = (R)(ae / (cf.cap * cf.dt));
+  const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
+  const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
+  const R dvn_dt = (tx * n0 + ty * n1 + tz * n2) * invl;
+  const R dvt_dt = (tx * t0 + ty * t1 + tz * t2) * invl;
+  const R dvn_dn = (nx * n0 + ny * n1 + nz * n2) * invlr;
+  const R dvt_dn = (nx * t0 + ny * t1 + nz * t2) * invlr;
+  const R a = dvn_dn - dvt_dt, b = dvt_dn + dvn_dt;
+  const R def = sqrt(a * a + b * b);
+  return fmin(smag * def, cap);
+}
+// divergence at cell c of an edge field row
+template <typename R>
+__device__ __forceinline__ R dif_div(const DevGrid& g, const R* row, int c) {
+  const int i0 = g.c2e[c], i1 = g.c2e[g.cs + c], i2 = g.c2e[2 * g.cs + c];
+  const R k0 = (R)g.kdiv[c], k1 = (R)g.kdiv[g.cs + c], k2 = (R)g.kdiv[2 * g.cs + c];
+  return k0 * row[i0] + k1 * row[i1] + k2 * row[i2];
+}
+// relative vorticity at vertex v of an edge field row
+template <typename R>
+__device__ __forceinline__ R dif_curl(const DevGrid& g, const R* row, int v) {
+  R z = (R)g.kcurl[v] * row[g.v2e[v]];
+#pragma unroll
+  for (int s = 1; s < 6; ++s) z += (R)g.kcurl[s * g.vs + v] * row[g.v2e[s * g.vs + v]];
+  return z;
+}
+// second Laplacian at edge e from div(L1) at cells and curl(L1) at vertices
+template <typename R>
+__device__ __forceinline__ R dif_l2(const DevGrid& g, R dl1_c0, R dl1_c1, R cl1_v0, R cl1_v1, int e) {
+  const R invd = (R)g.invd[e], invl = (R)g.invl[e];
+  return (dl1_c1 - dl1_c0) * invd - (cl1_v1 - cl1_v0) * invl;
+}
+template <typename R>
+__device__ __forceinline__ R dif_update(R vn, R dt, R nu, R l1, R k4a2, R l2) {
+  return vn + dt * nu * l1 - k4a2 * l2;
+}
+// w at cell c, half level k after Smagorinsky diffusion with the edge
+// viscosity nu (averaged to the cell and the half level)
+template <typename R>
+__device__ __forceinline__ double dif_w(const DevGrid& g, const double* w_in, const R* nu, int c, int k,
+                                        const StepCoef& cf) {
+  const size_t r = (size_t)k * g.cs + c;
+  double wn = w_in[r];
+  if (cf.diffuse_w && k >= 1 && k <= g.K - 1) {
+    const R* na = nu + (size_t)(k - 1) * g.es;
+    const R* nbr = nu + (size_t)k * g.es;
+    R nuc = R(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int ie = g.c2e[i * g.cs + c];
+      nuc += R(0.5) * (na[ie] + nbr[ie]);
+    }
+    nuc = nuc / R(3);
+    const double* wr = w_in + (size_t)k * g.cs;
+    double lw = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) lw += g.klap[i * g.cs + c] * (wr[g.c2e2c[i * g.cs + c]] - wn);
+    wn = wn + cf.dt * (double)nuc * lw;
+  }
+  return wn;
+}
+
 template <typename R>
 struct BDvert {
   struct Args {
@@ -684,34 +771,14 @@ struct BDedge1 {
     const int kb = args.kb;
     const int e = bx * blockDim.x + threadIdx.x;
     if (e >= g.ne) return;
-    const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
-    int rv[4];
-  #pragma unroll
-    for (int i = 0; i < 4; ++i) rv[i] = g.e2c2v[i * g.es + e];
-    const R invd = (R)g.invd[e], invl = (R)g.invl[e], invlr = (R)g.invlr[e];
-    const R n0 = (R)g.nrm[e], n1 = (R)g.nrm[g.es + e], n2 = (R)g.nrm[2 * g.es + e];
-    const R t0 = (R)g.tan[e], t1 = (R)g.tan[g.es + e], t2 = (R)g.tan[2 * g.es + e];
-    const double ae = g.ae[e];
-    const R smag = (R)(cf.cs * ae);
-    const R cap = (R)(ae / (cf.cap * cf.dt));
     const size_t plane = (size_t)g.K * g.vs;
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
     for (int k = k0; k < k1; ++k) {
       const R* dr = dv + (size_t)k * g.cs;
       const R* zr = zeta + (size_t)k * g.vs;
-      l1[(size_t)k * g.es + e] = (dr[c1] - dr[c0]) * invd - (zr[rv[1]] - zr[rv[0]]) * invl;
+      l1[(size_t)k * g.es + e] = dif_l1<R>(g, dr, zr, e);
       const R* vx = vv + (size_t)k * g.vs;
-      const R* vy = vx + plane;
-      const R* vz = vy + plane;
-      const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
-      const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
-      const R dvn_dt = (tx * n0 + ty * n1 + tz * n2) * invl;
-      const R dvt_dt = (tx * t0 + ty * t1 + tz * t2) * invl;
-      const R dvn_dn = (nx * n0 + ny * n1 + nz * n2) * invlr;
-      const R dvt_dn = (nx * t0 + ny * t1 + nz * t2) * invlr;
-      const R a = dvn_dn - dvt_dt, b = dvt_dn + dvn_dt;
-      const R def = sqrt(a * a + b * b);
-      nu[(size_t)k * g.es + e] = fmin(smag * def, cap);
+      nu[(size_t)k * g.es + e] = dif_nu<R>(g, vx, vx + plane, vx + 2 * plane, e, cf);
     }
   }
 };
@@ -760,24 +827,10 @@ struct BDcv2 {
       for (int k = k0; k < k1; ++k) {
         if (k < K) {
           const R* row = l1 + (size_t)k * g.es;
-          divl1[(size_t)k * g.cs + c] = kd[0] * row[ie[0]] + kd[1] * row[ie[1]] + kd[2] * row[ie[2]];
+          divl1[(size_t)k * g.cs + c] = dif_div<R>(g, row, c);
         }
         const size_t r = (size_t)k * g.cs + c;
-        double wn = w_in[r];
-        if (cf.diffuse_w && k >= 1 && k <= K - 1) {
-          const R* na = nu + (size_t)(k - 1) * g.es;
-          const R* nbr = nu + (size_t)k * g.es;
-          R nuc = R(0);
-  #pragma unroll
-          for (int i = 0; i < 3; ++i) nuc += R(0.5) * (na[ie[i]] + nbr[ie[i]]);
-          nuc = nuc / R(3);
-          const double* wr = w_in + (size_t)k * g.cs;
-          double lw = 0.0;
-  #pragma unroll
-          for (int i = 0; i < 3; ++i) lw += kl[i] * (wr[nb[i]] - wn);
-          wn = wn + cf.dt * (double)nuc * lw;
-        }
-        w_out[r] = wn;
+        w_out[r] = dif_w<R>(g, w_in, nu, c, k, cf);
       }
     } else {
       const int v = (bx - ncb) * blockDim.x + threadIdx.x;
@@ -791,11 +844,7 @@ struct BDcv2 {
       }
       const int k0 = by * kb, k1 = min(K, k0 + kb);
       for (int k = k0; k < k1; ++k) {
-        const R* row = l1 + (size_t)k * g.es;
-        R z = cc[0] * row[idx[0]];
-  #pragma unroll
-        for (int s = 1; s < 6; ++s) z += cc[s] * row[idx[s]];
-        curll1[(size_t)k * g.vs + v] = z;
+        curll1[(size_t)k * g.vs + v] = dif_curl<R>(g, l1 + (size_t)k * g.es, v);
       }
     }
   }
@@ -826,7 +875,6 @@ struct BDedge2 {
     if (e >= g.ne) return;
     const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
     const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
-    const R invd = (R)g.invd[e], invl = (R)g.invl[e];
     const double ae = g.ae[e];
     const R k4a2 = (R)(cf.k4 * ae * ae);
     const R dt = (R)cf.dt;
@@ -834,9 +882,9 @@ struct BDedge2 {
     for (int k = k0; k < k1; ++k) {
       const R* dr = divl1 + (size_t)k * g.cs;
       const R* zr = curll1 + (size_t)k * g.vs;
-      const R l2 = (dr[c1] - dr[c0]) * invd - (zr[v1] - zr[v0]) * invl;
+      const R l2 = dif_l2<R>(g, dr[c0], dr[c1], zr[v0], zr[v1], e);
       const size_t r = (size_t)k * g.es + e;
-      vn[r] = vn[r] + dt * nu[r] * l1[r] - k4a2 * l2;
+      vn[r] = dif_update<R>(vn[r], dt, nu[r], l1[r], k4a2, l2);
     }
   }
 };

@@ -12,6 +12,10 @@
 #include "internal.h"
 #include "kernels.h"
 
+namespace dc {
+struct SurCtx;  // surrogate settings of a state (defined with the surrogate)
+}
+
 struct dc_grid {
   using HostGrid = dc::HostGrid;
   using DevGrid = dc::DevGrid;
@@ -43,6 +47,15 @@ struct dc_state {
   size_t ws_bytes = 0;
   void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
   double *wstar, *wtmp, *fe, *tau, *diag_part, *diag_out;
+  // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
+  // held viscosity [K][es], judge and range flags [es], counters [4]
+  dc::SurCtx* sur = nullptr;
+  void* sur_tmlp = nullptr;
+  void* sur_nu = nullptr;
+  int* sur_fj = nullptr;
+  int* sur_fr = nullptr;
+  int* sur_cnt = nullptr;
+  double sur_lbar = 1.0, sur_dbar = 1.0;  // mean primal / dual edge length
 };
 
 
@@ -94,6 +107,23 @@ Bufs<R> substep_bufs(const dc_state* s, int cur_idx, bool w_to_staging) {
   b.th_out = static_cast<double*>(nxt.theta_v);
   return b;
 }
+
+// The nsub dynamic substeps of one step (flipping the buffer set after
+// each); the last writes w to the diffusion staging field if to_staging.
+template <typename R>
+void enqueue_substeps(dc_state* s, const StepCoef& c, int nsub, bool to_staging) {
+  for (int i = 0; i < nsub; ++i) {
+    const Bufs<R> b = substep_bufs<R>(s, s->cur, i == nsub - 1 && to_staging);
+    launch_substep<R>(s->d, b, c, s->tiles, s->stream, &s->prof);
+    s->cur ^= 1;
+  }
+}
+
+// surrogate diffusion of the current buffer set (a state with an MLP set)
+template <typename R>
+void surrogate_diffusion(dc_state* s, const StepCoef& c);
+void surrogate_free(dc_state* s);
+void surrogate_geometry(dc_state* s);
 
 // Default launch tiles: levels per block so that each launch has a few
 // thousand blocks when the grid is large, one level per block on small grids.

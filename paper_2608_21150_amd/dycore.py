@@ -24,6 +24,10 @@ TABLES = ("e2c", "c2e", "e2v", "c2e2c", "c2v", "v2e", "v2c", "e2c2e", "e2c2v", "
 _p = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+MLP_NPARAMS = 5441
+MLP_NFEATURES = 18
 
 
 class GridDesc(ctypes.Structure):
@@ -60,17 +64,47 @@ class Fields(ctypes.Structure):
 
 class Diag(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double), ("theta_mass", ctypes.c_double), ("max_abs_w", ctypes.c_double),
-                ("max_abs_vn", ctypes.c_double), ("n_nonfinite", ctypes.c_int64)]
+                ("max_abs_vn", ctypes.c_double), ("n_nonfinite", ctypes.c_int64),
+                ("fallback_fraction", ctypes.c_double)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("epochs", ctypes.c_int32), ("lr0", ctypes.c_double),
+                ("lr1", ctypes.c_double), ("seed", ctypes.c_uint64), ("shuffle", ctypes.c_int32),
+                ("augment", ctypes.c_int32)]
+
+
+class SurrogateInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("judge_steps", ctypes.c_int64), ("judge_flagged", ctypes.c_int64),
+                ("range_flagged", ctypes.c_int64), ("fallback", ctypes.c_int64), ("n_columns", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("calls", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+def _hip_runtimes() -> set:
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    except OSError:
+        return set()
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or python -m paper_2608_21150_amd.build")
+    # PyTorch ships its own HIP runtime with the same soname as the system
+    # one.  Loading torch first makes this library bind to that copy, so the
+    # process holds a single runtime; two runtimes cannot share the device.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise RuntimeError("two HIP runtimes are loaded (%s): import torch before any other HIP library"
+                           % ", ".join(sorted(rts)))
     sig = {
         "dc_last_error": (ctypes.c_char_p, []),
         "dc_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
@@ -97,6 +131,21 @@ def _load():
         "dc_ensemble_step_eager": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
         "dc_ensemble_autotune": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32, ctypes.c_char_p]),
         "dc_ensemble_schedule": (ctypes.c_int, [_p, ctypes.c_char_p, ctypes.c_size_t]),
+        "dc_mlp_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.POINTER(_p)]),
+        "dc_mlp_destroy": (ctypes.c_int, [_p]),
+        "dc_mlp_get_params": (ctypes.c_int, [_p, _f32p, ctypes.c_int64]),
+        "dc_mlp_set_params": (ctypes.c_int, [_p, _f32p, ctypes.c_int64]),
+        "dc_mlp_set_norm": (ctypes.c_int, [_p, _f32p, _f32p, _f32p, _f32p, ctypes.c_float]),
+        "dc_mlp_get_norm": (ctypes.c_int, [_p, _f32p, ctypes.c_int64]),
+        "dc_mlp_fit_norm": (ctypes.c_int, [_p, _p, ctypes.c_int64, ctypes.c_int64]),
+        "dc_mlp_train": (ctypes.c_int, [_p, _p, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(TrainCfg)]),
+        "dc_mlp_loss_trace": (ctypes.c_int, [_p, _f32p, ctypes.c_int64, _i64p]),
+        "dc_mlp_forward": (ctypes.c_int, [_p, _f32p, ctypes.c_int64, _f32p]),
+        "dc_mlp_grad": (ctypes.c_int, [_p, _f32p, _f32p, ctypes.c_int64, _f32p, _f32p]),
+        "dc_state_set_mlp": (ctypes.c_int, [_p, _p, ctypes.c_double, ctypes.c_int32]),
+        "dc_surrogate_stats": (ctypes.c_int, [_p, ctypes.POINTER(SurrogateInfo)]),
+        "dc_surrogate_collect": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                                                _p, ctypes.c_int64, ctypes.c_int64, _i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -253,6 +302,26 @@ class State:
         check(lib.dc_diag_conservation(self.handle, ctypes.byref(d)))
         return {n: getattr(d, n) for n, _ in Diag._fields_}
 
+    def set_mlp(self, mlp: "Mlp", threshold: float = 1e-3, judge_every: int = 10):
+        check(lib.dc_state_set_mlp(self.handle, mlp.handle, float(threshold), int(judge_every)))
+        self._mlp = mlp  # keep the network alive while the state uses it
+
+    def surrogate_stats(self) -> dict:
+        info = SurrogateInfo()
+        check(lib.dc_surrogate_stats(self.handle, ctypes.byref(info)))
+        return {n: getattr(info, n) for n, _ in SurrogateInfo._fields_}
+
+    def collect(self, dt: float, nsub: int, seed: int, n_samples: int, buf, offset: int = 0,
+                return_index: bool = False):
+        """One plain step recording n_samples (features, tendency) pairs into
+        columns offset.. of buf, a float32 device tensor of shape (19, stride)."""
+        assert buf.dtype == self.torch.float32 and buf.dim() == 2 and buf.shape[0] == 19 and buf.is_contiguous()
+        idx = np.empty(n_samples, dtype=np.int64) if return_index else None
+        check(lib.dc_surrogate_collect(self.handle, float(dt), int(nsub), int(seed), int(n_samples), buf.data_ptr(),
+                                       buf.shape[1], int(offset),
+                                       idx.ctypes.data_as(_i64p) if idx is not None else None))
+        return idx
+
     def profile(self, enable: bool):
         check(lib.dc_state_profile(self.handle, 1 if enable else 0))
 
@@ -307,3 +376,84 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """The diffusion surrogate network: FP32 master weights on the GPU."""
+
+    def __init__(self, seed: int = 0):
+        h = _p()
+        check(lib.dc_mlp_create(int(seed), ctypes.byref(h)))
+        self.handle = h
+
+    def params(self) -> np.ndarray:
+        a = np.empty(MLP_NPARAMS, dtype=np.float32)
+        check(lib.dc_mlp_get_params(self.handle, a.ctypes.data_as(_f32p), a.size))
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        check(lib.dc_mlp_set_params(self.handle, a.ctypes.data_as(_f32p), a.size))
+
+    def set_norm(self, mean, std, fmin, fmax, target_std: float):
+        arrs = [np.ascontiguousarray(x, dtype=np.float32) for x in (mean, std, fmin, fmax)]
+        check(lib.dc_mlp_set_norm(self.handle, *[x.ctypes.data_as(_f32p) for x in arrs], float(target_std)))
+
+    def norm(self) -> dict:
+        a = np.empty(4 * MLP_NFEATURES + 1, dtype=np.float32)
+        check(lib.dc_mlp_get_norm(self.handle, a.ctypes.data_as(_f32p), a.size))
+        F = MLP_NFEATURES
+        return {"mean": a[:F], "std": a[F:2 * F], "min": a[2 * F:3 * F], "max": a[3 * F:4 * F], "target_std": a[4 * F]}
+
+    def fit_norm(self, buf, n: int):
+        check(lib.dc_mlp_fit_norm(self.handle, buf.data_ptr(), buf.shape[1], int(n)))
+
+    def train(self, buf, n: int, batch: int = 4096, epochs: int = 2, lr0: float = 1e-3, lr1: float = 1e-5,
+              seed: int = 0, shuffle: bool = True, augment: bool = True) -> np.ndarray:
+        cfg = TrainCfg(batch, epochs, lr0, lr1, seed, 1 if shuffle else 0, 1 if augment else 0)
+        check(lib.dc_mlp_train(self.handle, buf.data_ptr(), buf.shape[1], int(n), ctypes.byref(cfg)))
+        cnt = ctypes.c_int64()
+        check(lib.dc_mlp_loss_trace(self.handle, None, 0, ctypes.byref(cnt)))
+        tr = np.empty(cnt.value, dtype=np.float32)
+        check(lib.dc_mlp_loss_trace(self.handle, tr.ctypes.data_as(_f32p), tr.size, ctypes.byref(cnt)))
+        return tr
+
+    def forward(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.empty(x.shape[0], dtype=np.float32)
+        check(lib.dc_mlp_forward(self.handle, x.ctypes.data_as(_f32p), x.shape[0], y.ctypes.data_as(_f32p)))
+        return y
+
+    def grad(self, x, t):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        g = np.empty(MLP_NPARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        check(lib.dc_mlp_grad(self.handle, x.ctypes.data_as(_f32p), t.ctypes.data_as(_f32p), x.shape[0],
+                              g.ctypes.data_as(_f32p), ctypes.byref(loss)))
+        return g, loss.value
+
+    def close(self):
+        if self.handle:
+            check(lib.dc_mlp_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_pack(p: dict) -> np.ndarray:
+    """Flatten a parameter dict (w1, b1, w2, b2, w3, b3) in the library's order."""
+    return np.concatenate([np.asarray(p[k], dtype=np.float64).reshape(-1)
+                           for k in ("w1", "b1", "w2", "b2", "w3", "b3")]).astype(np.float32)
+
+
+def mlp_unpack(a) -> dict:
+    a = np.asarray(a)
+    F, H = MLP_NFEATURES, 64
+    o = np.cumsum([0, F * H, H, H * H, H, H, 1])
+    return {"w1": a[o[0]:o[1]].reshape(F, H), "b1": a[o[1]:o[2]], "w2": a[o[2]:o[3]].reshape(H, H),
+            "b2": a[o[3]:o[4]], "w3": a[o[4]:o[5]], "b3": a[o[5]:o[6]]}
