@@ -218,8 +218,12 @@ def vertex_lsq_weights(g):
     return P @ np.linalg.pinv(NP)  # (V, 3, 6)
 
 
-def smagorinsky_nu(g, p, vv, dt):
-    """Smagorinsky viscosity from the rhombus deformation (edges), capped for stability."""
+def rhombus_derivatives(g, vv):
+    """Derivatives of the normal and tangential wind across the rhombus of
+    each edge, from the vertex vectors vv (K, V, 3): along the edge (between
+    its end vertices, over l_e) and across it (between the two opposite
+    vertices, over their great-circle distance).  Returns dvn_dt, dvt_dt,
+    dvn_dn, dvt_dn, each (K, E)."""
     R = g.radius
     v0, v1, v2, v3 = (g.e2c2v[:, i] for i in range(4))
     big_l = R * np.arctan2(np.linalg.norm(np.cross(g.xv[v2], g.xv[v3]), axis=1),
@@ -230,6 +234,19 @@ def smagorinsky_nu(g, p, vv, dt):
     dvt_dt = np.einsum("kej,ej->ke", d_t, g.tan) / g.l_e
     dvn_dn = np.einsum("kej,ej->ke", d_n, g.nrm) / big_l
     dvt_dn = np.einsum("kej,ej->ke", d_n, g.tan) / big_l
+    return dvn_dt, dvt_dt, dvn_dn, dvt_dn
+
+
+def vertex_vectors(g, vn, wts):
+    """Least-squares vertex vectors (K, V, 3) of the normal winds vn."""
+    ok = g.v2e >= 0
+    vn_v = np.where(ok[None], vn[:, np.maximum(g.v2e, 0)], 0.0)  # (K, V, 6)
+    return np.einsum("vjs,kvs->kvj", wts, vn_v)
+
+
+def smagorinsky_nu(g, p, vv, dt):
+    """Smagorinsky viscosity from the rhombus deformation (edges), capped for stability."""
+    dvn_dt, dvt_dt, dvn_dn, dvt_dn = rhombus_derivatives(g, vv)
     deform = np.sqrt((dvn_dn - dvt_dt) ** 2 + (dvt_dn + dvn_dt) ** 2)
     return np.minimum(p["smag_cs"] * g.a_e * deform, g.a_e / (p["smag_cap"] * dt))
 
@@ -239,9 +256,7 @@ def diffusion(g, p, S, dt, wts=None):
         wts = vertex_lsq_weights(g)
     K = g.n_lev
     vn = S["vn"]
-    ok = g.v2e >= 0
-    vn_v = np.where(ok[None], vn[:, np.maximum(g.v2e, 0)], 0.0)  # (K, V, 6)
-    vv = np.einsum("vjs,kvs->kvj", wts, vn_v)  # (K, V, 3)
+    vv = vertex_vectors(g, vn, wts)
     nu = smagorinsky_nu(g, p, vv, dt)
     l1 = op.lapv(g, vn)
     l2 = op.lapv(g, l1)

@@ -93,25 +93,40 @@ def cosine_lr(step, total, lr0=1e-3, lr1=1e-5):
     return lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * step / max(total, 1)))
 
 
-def features(g, vn):
+def features(g, vn, wts=None):
     """The 18 features of every (level, edge): (K, E, 18), in this order:
-    vn_e, vt_e, vn at the 4 e2c2e edges, vt at the 4 e2c2e edges, div vn at
-    c0 and c1, relative vorticity at the 4 e2c2v vertices, l_e / mean l,
-    d_e / mean d."""
+    0 vn_e, 1 vt_e; 2, 3 div vn at c0, c1; 4, 5 curl vn at the end vertices
+    v0, v1; 6, 7 div L1 at c0, c1 and 8, 9 curl L1 at v0, v1, with
+    L1 = lapv(vn) = grad div vn - gradt curl vn; 10..13 the rhombus
+    derivatives dvn_dt, dvt_dt, dvn_dn, dvt_dn of the least-squares vertex
+    vectors; 14, 15 curl vn at the two opposite rhombus vertices; 16 l_e /
+    mean l, 17 d_e / mean d.  Features 0..15 are linear in vn (odd in the
+    flow); the second Laplacian and the Smagorinsky deformation of the
+    diffusion are functions of features 2..13 and the edge geometry."""
+    from . import dycore as dy
+
+    if wts is None:
+        wts = dy.vertex_lsq_weights(g)
     vt = op.recon_vt(g, vn)
     D = op.div(g, vn)
     z = op.curl(g, vn)
+    L1 = op.lapv(g, vn)
+    dL1 = op.div(g, L1)
+    cL1 = op.curl(g, L1)
+    der = dy.rhombus_derivatives(g, dy.vertex_vectors(g, vn, wts))
     K, E = vn.shape
+    c0, c1 = g.e2c[:, 0], g.e2c[:, 1]
+    v0, v1, v2, v3 = (g.e2c2v[:, i] for i in range(4))
     f = np.empty((K, E, 18))
     f[:, :, 0] = vn
     f[:, :, 1] = vt
+    f[:, :, 2], f[:, :, 3] = D[:, c0], D[:, c1]
+    f[:, :, 4], f[:, :, 5] = z[:, v0], z[:, v1]
+    f[:, :, 6], f[:, :, 7] = dL1[:, c0], dL1[:, c1]
+    f[:, :, 8], f[:, :, 9] = cL1[:, v0], cL1[:, v1]
     for i in range(4):
-        f[:, :, 2 + i] = vn[:, g.e2c2e[:, i]]
-        f[:, :, 6 + i] = vt[:, g.e2c2e[:, i]]
-    f[:, :, 10] = D[:, g.e2c[:, 0]]
-    f[:, :, 11] = D[:, g.e2c[:, 1]]
-    for i in range(4):
-        f[:, :, 12 + i] = z[:, g.e2c2v[:, i]]
+        f[:, :, 10 + i] = der[i]
+    f[:, :, 14], f[:, :, 15] = z[:, v2], z[:, v3]
     f[:, :, 16] = (g.l_e / g.l_e.mean())[None, :]
     f[:, :, 17] = (g.d_e / g.d_e.mean())[None, :]
     return f

@@ -75,17 +75,71 @@ def test_features_definitions():
     g0 = make_grid(2, 1)
     S, vert = initial_state(g0, 3, 10e3, seed=2, vn_sigma=1.0)
     g = Grid(g0, vert)
-    f = M.features(g, S["vn"])
+    vn = S["vn"]
+    f = M.features(g, vn)
     e, k = 17, 1
-    vt = op.recon_vt(g, S["vn"])
-    assert f[k, e, 0] == S["vn"][k, e] and f[k, e, 1] == vt[k, e]
-    assert f[k, e, 3] == S["vn"][k, g.e2c2e[e, 1]]
-    D = op.div(g, S["vn"])
-    assert f[k, e, 11] == D[k, g.e2c[e, 1]]
-    z = op.curl(g, S["vn"])
-    assert f[k, e, 14] == z[k, g.e2c2v[e, 2]]
+    vt = op.recon_vt(g, vn)
+    assert f[k, e, 0] == vn[k, e] and f[k, e, 1] == vt[k, e]
+    D = op.div(g, vn)
+    assert f[k, e, 3] == D[k, g.e2c[e, 1]]
+    z = op.curl(g, vn)
+    assert f[k, e, 5] == z[k, g.e2c2v[e, 1]] and f[k, e, 15] == z[k, g.e2c2v[e, 3]]
     assert np.allclose(f[0, :, 16].mean(), 1.0) and np.allclose(f[0, :, 17].mean(), 1.0)
     # odd in the flow: flipping vn flips the 16 flow features, keeps geometry
-    f2 = M.features(g, -S["vn"])
+    f2 = M.features(g, -vn)
     assert np.allclose(f2[..., :16], -f[..., :16], rtol=0, atol=1e-12)
     assert np.array_equal(f2[..., 16:], f[..., 16:])
+
+
+def test_features_of_a_solid_body_rotation():
+    """A rigid rotation u = Omega x r: no divergence, vorticity 2 Omega
+    sin(latitude), no deformation (closed forms, up to discretisation)."""
+    from oracle.grid import Grid
+    from synth import initial_state, make_grid
+
+    g0 = make_grid(2, 2)
+    _, vert = initial_state(g0, 1, 10e3, seed=0)
+    g = Grid(g0, vert)
+    om = 1.0e-5
+    u = np.cross(np.array([0.0, 0.0, om * g.radius]), g.xe)  # (E, 3) metres/s
+    vn = np.einsum("ej,ej->e", u, g.nrm)[None, :]
+    f = M.features(g, vn)
+    scale_d = om  # natural size of the divergence and vorticity
+    assert np.max(np.abs(f[0, :, 2:4])) < 2e-2 * scale_d  # discretely almost divergence-free
+    lat = g.xv[:, 2]
+    z_ref = 2.0 * om * lat  # curl of a rigid rotation
+    zz = f[0, :, 4]
+    assert np.max(np.abs(zz - z_ref[g.e2c2v[:, 0]])) < 2e-2 * 2 * om
+    # deformation of a rigid rotation vanishes (the least-squares vertex
+    # vectors leave a discretisation error, largest near the 12 pentagons),
+    # while each shear derivative is of the size of the rotation rate: a sign
+    # error in the shearing combination would give |b| ~ Omega
+    a = f[0, :, 12] - f[0, :, 11]
+    b = f[0, :, 13] + f[0, :, 10]
+    d = np.hypot(a, b)
+    assert np.sqrt(np.mean(d**2)) < 0.1 * 2 * om and np.max(d) < 0.2 * 2 * om
+    assert np.median(np.abs(f[0, :, 13])) > 0.1 * om
+
+
+def test_features_determine_the_plain_tendency():
+    """The linear part of the diffusion tendency is an exact function of
+    features 2..9 and the geometry: -k4 A_e^2 / dt (grad divL1 - gradt curlL1)
+    + nu L1, with L1 = (D1 - D0)/d - (z1 - z0)/l, nu from features 10..13."""
+    from oracle import dycore as dy
+    from oracle.constants import default_params
+    from oracle.grid import Grid
+    from synth import initial_state, make_grid
+
+    g0 = make_grid(2, 1)
+    S, vert = initial_state(g0, 3, 10e3, seed=5, vn_sigma=2.0, jet_u0=20.0)
+    g = Grid(g0, vert)
+    p = default_params()
+    dt = 300.0
+    f = M.features(g, S["vn"])
+    T = M.diffusion_tendency(g, p, S, dt, dy.diffusion)
+    L1 = (f[..., 3] - f[..., 2]) / g.d_e - (f[..., 5] - f[..., 4]) / g.l_e
+    L2 = (f[..., 7] - f[..., 6]) / g.d_e - (f[..., 9] - f[..., 8]) / g.l_e
+    deform = np.hypot(f[..., 12] - f[..., 11], f[..., 13] + f[..., 10])
+    nu = np.minimum(p["smag_cs"] * g.a_e * deform, g.a_e / (p["smag_cap"] * dt))
+    T_f = nu * L1 - p["hdiff_k4"] * g.a_e**2 * L2 / dt
+    assert np.max(np.abs(T_f - T)) <= 1e-9 * np.max(np.abs(T))
