@@ -154,6 +154,109 @@ def bench_ensemble(args, D, torch):
     print(json.dumps(line), flush=True)
 
 
+def bench_surrogate(args, D, torch):
+    """The learned diffusion on R2B6 / 65 levels: collect training pairs from
+    plain FP64 steps, fit and train the network, then run the same number of
+    steps from a held-out initial state with (i) the plain diffusion, (ii) the
+    network with per-column fallback, (ii') the network without judge steps,
+    (iii) no vn diffusion (a zero network) and (iv) an untrained network;
+    report each run's error against (i) and its time per step."""
+    import numpy as np
+
+    from synth import build_workload, initial_state
+
+    name = "r2b6_k65"
+    g0, S_tr, vert, spec = build_workload(name)
+    S_ev, _ = initial_state(g0, spec["n_lev"], spec["z_top"], **dict(spec["state"], seed=5))
+    C, E, K = g0["n_cells"], g0["n_edges"], spec["n_lev"]
+    dt, nsub = spec["dt"], spec["nsub"]
+    G = D.Grid(g0, vert)
+    n_tr, per = args.train_steps, args.train_per_step
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    buf = torch.empty((19, n_tr * per), dtype=torch.float32, device="cuda")
+    st = D.State(G, diffusion="surrogate")
+    st.write(S_tr)
+    t0 = time.perf_counter()
+    for i in range(n_tr):
+        st.collect(dt, nsub, seed=(4 << 32) + i, n_samples=per, buf=buf, offset=i * per)
+        if (i + 1) % 50 == 0 or i + 1 == n_tr:
+            torch.cuda.synchronize()
+            log(f"collected {i + 1}/{n_tr} steps")
+    t_collect = time.perf_counter() - t0
+    st.close()
+    n = n_tr * per
+    net = D.Mlp(seed=3)
+    net.fit_norm(buf, n)
+    t0 = time.perf_counter()
+    trace = net.train(buf, n, batch=4096, epochs=2, lr0=1e-3, lr1=1e-5, seed=4)
+    t_train = time.perf_counter() - t0
+    log(f"trained {len(trace)} Adam steps in {t_train:.1f} s, loss {trace[:100].mean():.4g} -> {trace[-100:].mean():.4g}")
+    del buf
+    torch.cuda.empty_cache()
+    nrm = net.norm()
+    untrained = D.Mlp(seed=3)
+    untrained.set_norm(nrm["mean"], nrm["std"], nrm["min"], nrm["max"], nrm["target_std"])
+    zero = D.Mlp(seed=0)
+    zero.set_params(np.zeros(D.MLP_NPARAMS, dtype=np.float32))
+    inf = float("inf")
+
+    def run(label, mlp=None, thr=None, judge=None, steps=args.eval_steps):
+        s = D.State(G, diffusion="surrogate" if mlp is not None else "plain")
+        s.write(S_ev)
+        if mlp is not None:
+            s.set_mlp(mlp, thr, judge)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            s.step(dt, nsub)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out = s.read()
+        info = s.surrogate_stats() if mlp is not None else None
+        s.close()
+        log(f"{label}: {steps} steps, {ms:.3f} ms/step")
+        return ms, out, info
+
+    run("warm-up", net, 1e-3, 10, steps=3)
+    runs = {"plain": run("plain"),
+            "mlp_fallback": run("mlp_fallback", net, 1e-3, 10),
+            "mlp_no_judge": run("mlp_no_judge", net, inf, 1 << 30),
+            "no_vn_diffusion": run("no_vn_diffusion", zero, inf, 1 << 30),
+            "untrained_mlp": run("untrained_mlp", untrained, inf, 1 << 30)}
+    ref = runs["plain"][1]
+    res = {}
+    for k, (ms, out, info) in runs.items():
+        r = {"ms_per_step": ms, "rel_l2_vs_plain": {f: float(np.linalg.norm(out[f] - ref[f]) / np.linalg.norm(ref[f]))
+                                                    for f in FIELDS}}
+        if info is not None:
+            apply_steps = info["steps"] - info["judge_steps"]
+            r["judge_steps"] = info["judge_steps"]
+            r["mean_fallback_fraction"] = info["fallback_total"] / max(1, apply_steps * info["n_columns"])
+        res[k] = r
+    err = {k: res[k]["rel_l2_vs_plain"]["vn"] for k in res}
+    ms_sur, ms_plain = res["mlp_fallback"]["ms_per_step"], res["plain"]["ms_per_step"]
+    line = {"metric": METRIC, "value": C * K / (ms_sur * 1e-3), "unit": "cell·level·steps/s", "n_gpus": 1,
+            "steps": args.eval_steps, "warmup": 0, "ms_per_step": ms_sur, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+            "config": {"workload": f"surrogate: R2B6 icosahedral grid, {C} cells, {E} edges, {K} levels, dt {dt} s, "
+                                   f"{nsub} substeps, FP64 dycore; network trained on {n} pairs from {n_tr} plain "
+                                   f"steps (seed 3), evaluated over {args.eval_steps} steps from a held-out state "
+                                   f"(seed 5), threshold 1e-3, judge every 10 steps"},
+            "surrogate": {"runs": res, "speedup_vs_plain": ms_plain / ms_sur,
+                          "gain_test_pass": bool(err["mlp_fallback"] < err["no_vn_diffusion"]
+                                                 and err["mlp_fallback"] < err["untrained_mlp"]),
+                          "train": {"pairs": n, "adam_steps": len(trace), "collect_s": t_collect,
+                                    "train_s": t_train, "loss_first100": float(trace[:100].mean()),
+                                    "loss_last100": float(trace[-100:].mean())}}}
+    for m in (net, untrained, zero):
+        m.close()
+    G.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +266,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--sfc", type=int, default=-1, help="1/0 force the Morton renumbering; -1 workload default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=200, help="surrogate: plain steps that collect pairs")
+    ap.add_argument("--train-per-step", type=int, default=1_000_000, help="surrogate: pairs per collected step")
+    ap.add_argument("--eval-steps", type=int, default=500, help="surrogate: steps of every evaluation run")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration) and exit")
@@ -190,6 +296,8 @@ def main():
 
     if args.workload == "ensemble":
         return bench_ensemble(args, D, torch)
+    if args.workload == "surrogate":
+        return bench_surrogate(args, D, torch)
     spec = WORKLOADS[args.workload]
     sfc = bool(spec.get("sfc", 0)) if args.sfc < 0 else bool(args.sfc)
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)

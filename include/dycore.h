@@ -235,10 +235,18 @@ dc_status dc_ensemble_destroy(dc_ensemble *ens);
  * and 6); the network is this library's reading: per (edge, level) an
  * 18 -> 64 -> 64 -> 1 perceptron with exact (erf) GELU, BF16 operands on the
  * matrix cores and FP32 accumulation, predicting T = (vn after the vn
- * diffusion - vn before) / dt from 18 stencil features, in this order:
- *   vn_e, vt_e, vn of the 4 e2c2e edges, vt of the 4 e2c2e edges,
- *   div vn at e2c[0], e2c[1], curl vn at the 4 e2c2v vertices,
- *   l_e / mean(l), d_e / mean(d).
+ * diffusion - vn before) / dt from 18 stencil features.  Stencil values
+ * enter as centred pairs (mean of the two points, difference over their
+ * distance, formed before the BF16 rounding), in this order:
+ *   0 vn_e, 1 vt_e; 2, 3 D = div vn at e2c[0..1]; 4, 5 Z = curl vn at the
+ *   end vertices e2c2v[0..1]; 6, 7 div L1 at the two cells; 8, 9 curl L1 at
+ *   the two end vertices (L1 = grad D - gradt Z); 10..13 the rhombus
+ *   derivatives dvn/dt, dvt/dt, dvn/dn, dvt/dn of the least-squares vertex
+ *   vectors (the Smagorinsky deformation); 14, 15 Z at the opposite rhombus
+ *   vertices e2c2v[2..3] (difference over the rhombus diagonal);
+ *   16 l_e / mean(l), 17 d_e / mean(d).
+ * Features 0..15 are odd in vn; the plain tendency is nu L1 - k4 A_e^2 L2 / dt
+ * with L1 = f3 - f5, L2 = f7 - f9 and nu a function of f10..f13 and A_e.
  * Parameters (DC_MLP_NPARAMS floats, row-major): W1 [18][64], b1 [64],
  * W2 [64][64], b2 [64], w3 [64], b3 [1]; y = W3 gelu(W2 gelu(W1 x' + b1) + b2)
  * + b3 with x' = (x - mean) / std, and T = y * target_std.
@@ -270,6 +278,7 @@ typedef struct {
   int64_t judge_flagged;      /* columns flagged by the last judge step                        */
   int64_t range_flagged;      /* columns with out-of-range features in the last non-judge step  */
   int64_t fallback;           /* columns that ran the plain diffusion in that step              */
+  int64_t fallback_total;     /* the same summed over the non-judge steps since dc_state_set_mlp */
   int64_t n_columns;          /* edge columns of the grid                                        */
 } dc_surrogate_info;
 

@@ -218,16 +218,22 @@ def vertex_lsq_weights(g):
     return P @ np.linalg.pinv(NP)  # (V, 3, 6)
 
 
+def rhombus_diagonal(g):
+    """Great-circle distance (m) between the two vertices of each edge's
+    rhombus that are not on the edge."""
+    v2, v3 = g.e2c2v[:, 2], g.e2c2v[:, 3]
+    return g.radius * np.arctan2(np.linalg.norm(np.cross(g.xv[v2], g.xv[v3]), axis=1),
+                                 np.einsum("ij,ij->i", g.xv[v2], g.xv[v3]))
+
+
 def rhombus_derivatives(g, vv):
     """Derivatives of the normal and tangential wind across the rhombus of
     each edge, from the vertex vectors vv (K, V, 3): along the edge (between
     its end vertices, over l_e) and across it (between the two opposite
     vertices, over their great-circle distance).  Returns dvn_dt, dvt_dt,
     dvn_dn, dvt_dn, each (K, E)."""
-    R = g.radius
     v0, v1, v2, v3 = (g.e2c2v[:, i] for i in range(4))
-    big_l = R * np.arctan2(np.linalg.norm(np.cross(g.xv[v2], g.xv[v3]), axis=1),
-                           np.einsum("ij,ij->i", g.xv[v2], g.xv[v3]))
+    big_l = rhombus_diagonal(g)
     d_t = vv[:, v1] - vv[:, v0]  # (K, E, 3)
     d_n = vv[:, v3] - vv[:, v2]
     dvn_dt = np.einsum("kej,ej->ke", d_t, g.nrm) / g.l_e

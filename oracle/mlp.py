@@ -94,15 +94,24 @@ def cosine_lr(step, total, lr0=1e-3, lr1=1e-5):
 
 
 def features(g, vn, wts=None):
-    """The 18 features of every (level, edge): (K, E, 18), in this order:
-    0 vn_e, 1 vt_e; 2, 3 div vn at c0, c1; 4, 5 curl vn at the end vertices
-    v0, v1; 6, 7 div L1 at c0, c1 and 8, 9 curl L1 at v0, v1, with
-    L1 = lapv(vn) = grad div vn - gradt curl vn; 10..13 the rhombus
-    derivatives dvn_dt, dvt_dt, dvn_dn, dvt_dn of the least-squares vertex
-    vectors; 14, 15 curl vn at the two opposite rhombus vertices; 16 l_e /
-    mean l, 17 d_e / mean d.  Features 0..15 are linear in vn (odd in the
-    flow); the second Laplacian and the Smagorinsky deformation of the
-    diffusion are functions of features 2..13 and the edge geometry."""
+    """The 18 features of every (level, edge): (K, E, 18).  Stencil values
+    enter as centred pairs (mean over the two points, difference over their
+    distance), so that the differences that decide the tendency are formed
+    before the network's BF16 rounding:
+      0 vn_e, 1 vt_e;
+      2 mean of D = div vn at c0, c1,      3 (D_c1 - D_c0) / d_e;
+      4 mean of Z = curl vn at v0, v1,     5 (Z_v1 - Z_v0) / l_e;
+      6 mean of div L1 at c0, c1,          7 its difference / d_e;
+      8 mean of curl L1 at v0, v1,         9 its difference / l_e;
+        with L1 = lapv(vn) = grad D - gradt Z;
+      10..13 the rhombus derivatives dvn_dt, dvt_dt, dvn_dn, dvt_dn of the
+        least-squares vertex vectors;
+      14 mean of Z at the opposite rhombus vertices v2, v3,
+      15 (Z_v3 - Z_v2) / (their distance);
+      16 l_e / mean l, 17 d_e / mean d.
+    Features 0..15 are linear in vn (odd in the flow).  The plain tendency
+    is nu L1 - k4 A_e^2 L2 / dt with L1 = f3 - f5, L2 = f7 - f9 and nu a
+    function of f10..f13 and A_e."""
     from . import dycore as dy
 
     if wts is None:
@@ -120,13 +129,14 @@ def features(g, vn, wts=None):
     f = np.empty((K, E, 18))
     f[:, :, 0] = vn
     f[:, :, 1] = vt
-    f[:, :, 2], f[:, :, 3] = D[:, c0], D[:, c1]
-    f[:, :, 4], f[:, :, 5] = z[:, v0], z[:, v1]
-    f[:, :, 6], f[:, :, 7] = dL1[:, c0], dL1[:, c1]
-    f[:, :, 8], f[:, :, 9] = cL1[:, v0], cL1[:, v1]
+    f[:, :, 2], f[:, :, 3] = 0.5 * (D[:, c0] + D[:, c1]), (D[:, c1] - D[:, c0]) / g.d_e
+    f[:, :, 4], f[:, :, 5] = 0.5 * (z[:, v0] + z[:, v1]), (z[:, v1] - z[:, v0]) / g.l_e
+    f[:, :, 6], f[:, :, 7] = 0.5 * (dL1[:, c0] + dL1[:, c1]), (dL1[:, c1] - dL1[:, c0]) / g.d_e
+    f[:, :, 8], f[:, :, 9] = 0.5 * (cL1[:, v0] + cL1[:, v1]), (cL1[:, v1] - cL1[:, v0]) / g.l_e
     for i in range(4):
         f[:, :, 10 + i] = der[i]
-    f[:, :, 14], f[:, :, 15] = z[:, v2], z[:, v3]
+    f[:, :, 14] = 0.5 * (z[:, v2] + z[:, v3])
+    f[:, :, 15] = (z[:, v3] - z[:, v2]) / dy.rhombus_diagonal(g)
     f[:, :, 16] = (g.l_e / g.l_e.mean())[None, :]
     f[:, :, 17] = (g.d_e / g.d_e.mean())[None, :]
     return f

@@ -81,7 +81,7 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff)
     L.s_nu = take(K * h.es * r);
     L.s_fj = take((size_t)h.es * 4);
     L.s_fr = take((size_t)h.es * 4);
-    L.s_cnt = take(4 * 4);
+    L.s_cnt = take(8 * 4);  // 4 int counters, then one 64-bit counter
   }
   L.total = off;
   return L;
@@ -395,7 +395,7 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   hipError_t e2 = hipMemcpy(s->tau, tau.data(), tau.size() * 8, hipMemcpyHostToDevice);
   if (e1 == hipSuccess && e2 == hipSuccess && diff == DC_DIFF_SURROGATE) {
     // flags and counters start cleared (the first surrogate step judges)
-    e1 = hipMemset(w + L.s_fj, 0, L.s_cnt + 16 - L.s_fj);
+    e1 = hipMemset(w + L.s_fj, 0, L.s_cnt + 32 - L.s_fj);
   }
   if (e1 != hipSuccess || e2 != hipSuccess) {
     delete s;

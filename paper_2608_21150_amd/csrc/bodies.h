@@ -593,27 +593,34 @@ __device__ __forceinline__ R dif_l1(const DevGrid& g, const R* dr, const R* zr, 
   const R invd = (R)g.invd[e], invl = (R)g.invl[e];
   return (dr[c1] - dr[c0]) * invd - (zr[v1] - zr[v0]) * invl;
 }
-// Smagorinsky viscosity at edge e from the rhombus deformation of the vertex
-// vectors (vx, vy, vz: the three components at one level)
+// Derivatives of the normal and tangential wind across the rhombus of edge e
+// from the vertex vectors (vx, vy, vz: the three components at one level):
+// d = {dvn/dt, dvt/dt, dvn/dn, dvt/dn}
 template <typename R>
-__device__ __forceinline__ R dif_nu(const DevGrid& g, const R* vx, const R* vy, const R* vz, int e,
-                                    const StepCoef& cf) {
+__device__ __forceinline__ void dif_rhombus(const DevGrid& g, const R* vx, const R* vy, const R* vz, int e, R d[4]) {
   int rv[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) rv[i] = g.e2c2v[i * g.es + e];
   const R invl = (R)g.invl[e], invlr = (R)g.invlr[e];
   const R n0 = (R)g.nrm[e], n1 = (R)g.nrm[g.es + e], n2 = (R)g.nrm[2 * g.es + e];
   const R t0 = (R)g.tan[e], t1 = (R)g.tan[g.es + e], t2 = (R)g.tan[2 * g.es + e];
+  const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
+  const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
+  d[0] = (tx * n0 + ty * n1 + tz * n2) * invl;
+  d[1] = (tx * t0 + ty * t1 + tz * t2) * invl;
+  d[2] = (nx * n0 + ny * n1 + nz * n2) * invlr;
+  d[3] = (nx * t0 + ny * t1 + nz * t2) * invlr;
+}
+// Smagorinsky viscosity at edge e from the rhombus deformation
+template <typename R>
+__device__ __forceinline__ R dif_nu(const DevGrid& g, const R* vx, const R* vy, const R* vz, int e,
+                                    const StepCoef& cf) {
+  R d[4];
+  dif_rhombus<R>(g, vx, vy, vz, e, d);
   const double ae = g.ae[e];
   const R smag = (R)(cf.cs * ae);
   const R cap = (R)(ae / (cf.cap * cf.dt));
-  const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
-  const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
-  const R dvn_dt = (tx * n0 + ty * n1 + tz * n2) * invl;
-  const R dvt_dt = (tx * t0 + ty * t1 + tz * t2) * invl;
-  const R dvn_dn = (nx * n0 + ny * n1 + nz * n2) * invlr;
-  const R dvt_dn = (nx * t0 + ny * t1 + nz * t2) * invlr;
-  const R a = dvn_dn - dvt_dt, b = dvt_dn + dvn_dt;
+  const R a = d[2] - d[1], b = d[3] + d[0];
   const R def = sqrt(a * a + b * b);
   return fmin(smag * def, cap);
 }

@@ -145,25 +145,59 @@ __device__ void forward64(const SW& s, const bf16* xs, bf16* hs, float y[4][4]) 
   }
 }
 
-// The 18 raw features of edge e at one level (rows of vn and vt at edges,
-// D at cells, zeta at vertices): vn_e, vt_e, vn and vt at the four e2c2e
-// edges, D at c0 and c1, zeta at the four e2c2v vertices, l_e / mean l,
-// d_e / mean d.
+// div L1 at cell c and curl L1 at vertex v, with L1 at the edges evaluated
+// from the divergence (dr) and vorticity (zr) rows of one level: the plain
+// diffusion's expressions (its div and curl of the stored L1 row)
 template <typename R>
-__device__ __forceinline__ void features(const DevGrid& g, const R* vn, const R* vt, const R* D, const R* Z, int e,
-                                         double lbar, double dbar, float f[NIN]) {
-  f[0] = (float)vn[e];
-  f[1] = (float)vt[e];
+__device__ __forceinline__ R divl1_at(const DevGrid& g, const R* dr, const R* zr, int c) {
+  const int i0 = g.c2e[c], i1 = g.c2e[g.cs + c], i2 = g.c2e[2 * g.cs + c];
+  const R k0 = (R)g.kdiv[c], k1 = (R)g.kdiv[g.cs + c], k2 = (R)g.kdiv[2 * g.cs + c];
+  return k0 * dif_l1<R>(g, dr, zr, i0) + k1 * dif_l1<R>(g, dr, zr, i1) + k2 * dif_l1<R>(g, dr, zr, i2);
+}
+template <typename R>
+__device__ __forceinline__ R curll1_at(const DevGrid& g, const R* dr, const R* zr, int v) {
+  R z = (R)g.kcurl[v] * dif_l1<R>(g, dr, zr, g.v2e[v]);
+  for (int s = 1; s < 6; ++s) z += (R)g.kcurl[s * g.vs + v] * dif_l1<R>(g, dr, zr, g.v2e[s * g.vs + v]);
+  return z;
+}
+
+// The 18 raw features of edge e at level k, from vn, vt (edges), D = div vn
+// (cells), Z = curl vn and the vertex vectors V (vertices, three component
+// planes `plane` apart).  Stencil values enter as centred pairs, the mean of
+// the two points and their difference over their distance, formed in the
+// path's precision before the network's BF16 rounding: vn_e, vt_e; D at
+// c0, c1; Z at the end vertices v0, v1; div L1 at c0, c1; curl L1 at v0, v1;
+// the four rhombus derivatives; Z at the two opposite rhombus vertices;
+// l_e / mean l, d_e / mean d.
+template <typename R>
+__device__ __forceinline__ void features(const DevGrid& g, const R* vn, const R* vt, const R* D, const R* Z,
+                                         const R* V, size_t plane, int e, int k, double lbar, double dbar,
+                                         float f[NIN]) {
+  const R* dr = D + (size_t)k * g.cs;
+  const R* zr = Z + (size_t)k * g.vs;
+  const R* vx = V + (size_t)k * g.vs;
+  const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
+  const int v0 = g.e2c2v[e], v1 = g.e2c2v[g.es + e], v2 = g.e2c2v[2 * g.es + e], v3 = g.e2c2v[3 * g.es + e];
+  const R invd = (R)g.invd[e], invl = (R)g.invl[e], invlr = (R)g.invlr[e];
+  const R half = R(0.5);
+  f[0] = (float)vn[(size_t)k * g.es + e];
+  f[1] = (float)vt[(size_t)k * g.es + e];
+  f[2] = (float)(half * (dr[c0] + dr[c1]));
+  f[3] = (float)((dr[c1] - dr[c0]) * invd);
+  f[4] = (float)(half * (zr[v0] + zr[v1]));
+  f[5] = (float)((zr[v1] - zr[v0]) * invl);
+  const R a0 = divl1_at<R>(g, dr, zr, c0), a1 = divl1_at<R>(g, dr, zr, c1);
+  f[6] = (float)(half * (a0 + a1));
+  f[7] = (float)((a1 - a0) * invd);
+  const R b0 = curll1_at<R>(g, dr, zr, v0), b1 = curll1_at<R>(g, dr, zr, v1);
+  f[8] = (float)(half * (b0 + b1));
+  f[9] = (float)((b1 - b0) * invl);
+  R d[4];
+  dif_rhombus<R>(g, vx, vx + plane, vx + 2 * plane, e, d);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int x = g.e2c2e[i * g.es + e];
-    f[2 + i] = (float)vn[x];
-    f[6 + i] = (float)vt[x];
-  }
-  f[10] = (float)D[g.e2c[e]];
-  f[11] = (float)D[g.e2c[g.es + e]];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) f[12 + i] = (float)Z[g.e2c2v[i * g.es + e]];
+  for (int i = 0; i < 4; ++i) f[10 + i] = (float)d[i];
+  f[14] = (float)(half * (zr[v2] + zr[v3]));
+  f[15] = (float)((zr[v3] - zr[v2]) * invlr);
   f[16] = (float)(1.0 / (g.invl[e] * lbar));
   f[17] = (float)(1.0 / (g.invd[e] * dbar));
 }
@@ -190,7 +224,7 @@ __global__ void __launch_bounds__(256) k_vt(DevGrid g, const R* __restrict__ vn,
 template <typename R>
 __global__ void __launch_bounds__(128) k_infer(DevGrid g, const R* __restrict__ vn, const R* __restrict__ vt,
                                                const R* __restrict__ D, const R* __restrict__ Z,
-                                               const float* __restrict__ par, const Norm* __restrict__ nrm,
+                                               const R* __restrict__ V, const float* __restrict__ par, const Norm* __restrict__ nrm,
                                                double lbar, double dbar, R* __restrict__ tout,
                                                int* __restrict__ flag_range) {
   __shared__ SW s;
@@ -208,8 +242,7 @@ __global__ void __launch_bounds__(128) k_infer(DevGrid g, const R* __restrict__ 
     const int e = e0 + l;
     float f[NIN];
     if (e < g.ne) {
-      features<R>(g, vn + (size_t)k * g.es, vt + (size_t)k * g.es, D + (size_t)k * g.cs, Z + (size_t)k * g.vs, e,
-                  lbar, dbar, f);
+      features<R>(g, vn, vt, D, Z, V, (size_t)g.K * g.vs, e, k, lbar, dbar, f);
       bool out = false;
 #pragma unroll
       for (int i = 0; i < NIN; ++i) out |= !(f[i] >= nrm->fmin[i] && f[i] <= nrm->fmax[i]);
@@ -248,14 +281,8 @@ __device__ R plain_vn(const DevGrid& g, R vn, const R* D, const R* Z, const R* V
   const R nu = dif_nu<R>(g, vx, vx + plane, vx + 2 * plane, e, cf);
   R dl[2], cl[2];
   for (int side = 0; side < 2; ++side) {
-    const int c = g.e2c[side * g.es + e];
-    const int i0 = g.c2e[c], i1 = g.c2e[g.cs + c], i2 = g.c2e[2 * g.cs + c];
-    const R k0 = (R)g.kdiv[c], k1 = (R)g.kdiv[g.cs + c], k2 = (R)g.kdiv[2 * g.cs + c];
-    dl[side] = k0 * dif_l1<R>(g, dr, zr, i0) + k1 * dif_l1<R>(g, dr, zr, i1) + k2 * dif_l1<R>(g, dr, zr, i2);
-    const int v = g.e2v[side * g.es + e];
-    R z = (R)g.kcurl[v] * dif_l1<R>(g, dr, zr, g.v2e[v]);
-    for (int s = 1; s < 6; ++s) z += (R)g.kcurl[s * g.vs + v] * dif_l1<R>(g, dr, zr, g.v2e[s * g.vs + v]);
-    cl[side] = z;
+    dl[side] = divl1_at<R>(g, dr, zr, g.e2c[side * g.es + e]);
+    cl[side] = curll1_at<R>(g, dr, zr, g.e2v[side * g.es + e]);
   }
   const R l2 = dif_l2<R>(g, dl[0], dl[1], cl[0], cl[1], e);
   const double ae = g.ae[e];
@@ -263,9 +290,21 @@ __device__ R plain_vn(const DevGrid& g, R vn, const R* D, const R* Z, const R* V
   return dif_update<R>(vn, (R)cf.dt, nu, l1e, (R)(cf.k4 * ae * ae), l2);
 }
 
+// Adds the wave's count of lanes with pred set to *c (one atomic per wave;
+// integer sums are order independent).  Every lane of the wave must call it.
+__device__ __forceinline__ void wave_count(bool pred, int* c) {
+  const unsigned long long b = __ballot(pred);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(c, (int)__popcll(b));
+}
+__device__ __forceinline__ void wave_count64(bool pred, unsigned long long* c) {
+  const unsigned long long b = __ballot(pred);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(c, (unsigned long long)__popcll(b));
+}
+
 // apply: vn += dt T_mlp, or the plain update on flagged columns (which also
-// refresh their held viscosity).  cnt[1] counts range flags, cnt[2]
-// fallback columns (integer atomics: order independent).
+// refresh their held viscosity).  cnt[1] counts range flags, cnt[2] fallback
+// columns of this step; the 64-bit counter at cnt + 4 sums the fallback
+// columns since the network was set.
 template <typename R>
 __global__ void __launch_bounds__(256) k_apply(DevGrid g, R* __restrict__ vn, const R* __restrict__ tmlp,
                                                const R* __restrict__ D, const R* __restrict__ Z,
@@ -273,12 +312,15 @@ __global__ void __launch_bounds__(256) k_apply(DevGrid g, R* __restrict__ vn, co
                                                const int* __restrict__ fj, const int* __restrict__ fr,
                                                int* __restrict__ cnt, StepCoef cf) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= g.ne) return;
-  const bool fb = (fj[e] | fr[e]) != 0;
-  if (fr[e]) atomicAdd(&cnt[1], 1);
+  const bool in = e < g.ne;
+  const bool rf = in && fr[e] != 0;
+  const bool fb = in && (rf || fj[e] != 0);
+  wave_count(rf, &cnt[1]);
+  wave_count(fb, &cnt[2]);
+  wave_count64(fb, reinterpret_cast<unsigned long long*>(cnt + 4));
+  if (!in) return;
   const size_t plane = (size_t)g.K * g.vs;
   if (fb) {
-    atomicAdd(&cnt[2], 1);
     for (int k = 0; k < g.K; ++k) {
       const size_t r = (size_t)k * g.es + e;
       R nu;
@@ -301,9 +343,9 @@ __global__ void __launch_bounds__(256) k_judge(DevGrid g, const R* __restrict__ 
                                                const R* __restrict__ tmlp, double dt, double thr,
                                                int* __restrict__ fj, int* __restrict__ cnt) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= g.ne) return;
+  const bool in = e < g.ne;
   double num = 0.0, den = 0.0;
-  for (int k = 0; k < g.K; ++k) {
+  for (int k = 0; in && k < g.K; ++k) {
     const size_t r = (size_t)k * g.es + e;
     const double tp = ((double)vn_new[r] - (double)vn_old[r]) / dt;
     const double d = (double)tmlp[r] - tp;
@@ -311,9 +353,9 @@ __global__ void __launch_bounds__(256) k_judge(DevGrid g, const R* __restrict__ 
     den += (double)vn_old[r] * (double)vn_old[r];
   }
   const double res = dt * sqrt(num) / fmax(sqrt(den), sqrt((double)g.K));
-  const int f = (res > thr || !(res == res)) ? 1 : 0;
-  fj[e] = f;
-  if (f) atomicAdd(&cnt[0], 1);
+  const int f = (in && (res > thr || !(res == res))) ? 1 : 0;
+  wave_count(f != 0, &cnt[0]);
+  if (in) fj[e] = f;
 }
 
 __global__ void k_fill_int(int* __restrict__ p, int n, int v) {
@@ -373,7 +415,8 @@ __host__ __device__ __forceinline__ unsigned long long feistel(unsigned long lon
 // flat internal index k * ne + e of every sample
 template <typename R>
 __global__ void __launch_bounds__(256) k_sample_feat(DevGrid g, const R* __restrict__ vn, const R* __restrict__ vt,
-                                                     const R* __restrict__ D, const R* __restrict__ Z, double lbar,
+                                                     const R* __restrict__ D, const R* __restrict__ Z,
+                                                     const R* __restrict__ V, double lbar,
                                                      double dbar, unsigned long long key, long long nsamp,
                                                      float* __restrict__ buf, long long stride, long long offset,
                                                      long long* __restrict__ idx_out) {
@@ -383,8 +426,7 @@ __global__ void __launch_bounds__(256) k_sample_feat(DevGrid g, const R* __restr
   const unsigned long long idx = feistel((unsigned long long)i, N, key);
   const int k = (int)(idx / g.ne), e = (int)(idx % g.ne);
   float f[NIN];
-  features<R>(g, vn + (size_t)k * g.es, vt + (size_t)k * g.es, D + (size_t)k * g.cs, Z + (size_t)k * g.vs, e, lbar,
-              dbar, f);
+  features<R>(g, vn, vt, D, Z, V, (size_t)g.K * g.vs, e, k, lbar, dbar, f);
   for (int x = 0; x < NIN; ++x) buf[x * stride + offset + i] = f[x];
   if (idx_out) idx_out[i] = (long long)idx;
 }
@@ -760,7 +802,8 @@ void surrogate_diffusion(dc_state* s, const StepCoef& c) {
   k_fill_int<<<(g.ne + 255) / 256, 256, 0, st>>>(s->sur_fr, g.ne, 0);
   const int total = ((g.ne + 127) / 128) * g.K;
   k_infer<R><<<std::min(total, 4096), 128, 0, st>>>(g, vn, static_cast<const R*>(s->vns), static_cast<const R*>(s->kc),
-                                                    static_cast<const R*>(s->zeta), sc.mlp->par, sc.mlp->nrm,
+                                                    static_cast<const R*>(s->zeta), static_cast<const R*>(s->vv),
+                                                    sc.mlp->par, sc.mlp->nrm,
                                                     s->sur_lbar, s->sur_dbar, tm, s->sur_fr);
   if (judge) {
     ++sc.judge_steps;
@@ -809,7 +852,8 @@ dc_status collect_impl(dc_state* s, double dt, int nsub, unsigned long long key,
   R* old = static_cast<R*>(s->sur_tmlp);
   prep_fields<R>(s, vn, st);
   k_sample_feat<R><<<(unsigned)((nsamp + 255) / 256), 256, 0, st>>>(
-      g, vn, static_cast<const R*>(s->vns), static_cast<const R*>(s->kc), static_cast<const R*>(s->zeta), s->sur_lbar,
+      g, vn, static_cast<const R*>(s->vns), static_cast<const R*>(s->kc), static_cast<const R*>(s->zeta),
+      static_cast<const R*>(s->vv), s->sur_lbar,
       s->sur_dbar, key, nsamp, buf, stride, offset, idx_dev);
   k_copy<R><<<1024, 256, 0, st>>>(vn, old, (size_t)g.K * g.es);
   launch_diffusion<R>(g, vn, s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt), static_cast<R*>(s->tvn0),
@@ -907,7 +951,7 @@ dc_status dc_mlp_set_norm(dc_mlp* M, const float* mean, const float* sd, const f
   if (!(tstd > 0.f) || !std::isfinite(tstd)) return mfail(DC_EINVAL, "target scale must be finite and > 0");
   Norm nr{};
   for (int i = 0; i < NIN; ++i) {
-    if (!(sd[i] > 0.f) || !std::isfinite(sd[i]) || !std::isfinite(mean[i]))
+    if (!(sd[i] > 0.f) || !std::isfinite(sd[i]) || !std::isfinite(1.0f / sd[i]) || !std::isfinite(mean[i]))
       return mfail(DC_EINVAL, "feature scales must be finite and > 0");
     if (!(fmin[i] <= fmax[i])) return mfail(DC_EINVAL, "feature range must have min <= max");
     nr.mean[i] = mean[i];
@@ -960,8 +1004,11 @@ dc_status dc_mlp_fit_norm(dc_mlp* M, const float* dev_buf, int64_t stride, int64
     // flow features and the target: symmetric set (sign augmentation)
     const bool flow = r < NFLOW || r == NIN;
     const double mu = flow ? 0.0 : s / n;
+    // the physical features span tens of orders of magnitude (div L1 is
+    // ~1e-17 s^-1 m^-2 on a global grid): only a vanishing or non-finite
+    // spread counts as constant
     double var = s2 / n - mu * mu;
-    if (!(var > 1e-30)) var = 1.0;
+    if (!(var > 0.0) || !std::isfinite(var) || !std::isfinite((float)(1.0 / std::sqrt(var)))) var = 1.0;
     if (r == NIN) {
       tstd = (float)std::sqrt(var);
       continue;
@@ -1082,20 +1129,25 @@ dc_status dc_state_set_mlp(dc_state* s, const dc_mlp* M, double threshold, int32
   s->sur->judge_every = judge_every;
   s->sur->steps = 0;
   s->sur->judge_steps = 0;
+  k_fill_int<<<1, 64, 0, s->stream>>>(s->sur_cnt, 6, 0);
+  ML_TRY(hipGetLastError());
   return DC_OK;
 }
 
 dc_status dc_surrogate_stats(dc_state* s, dc_surrogate_info* out) {
   if (!s || !out) return mfail(DC_EINVAL, "NULL argument");
   if (s->diff != DC_DIFF_SURROGATE) return mfail(DC_ESTATE, "state was not created with DC_DIFF_SURROGATE");
-  int cnt[3] = {0, 0, 0};
+  int cnt[6] = {0, 0, 0, 0, 0, 0};
   ML_TRY(hipStreamSynchronize(s->stream));
   ML_TRY(hipMemcpy(cnt, s->sur_cnt, sizeof(cnt), hipMemcpyDeviceToHost));
+  unsigned long long total;
+  std::memcpy(&total, cnt + 4, sizeof(total));
   out->steps = s->sur ? s->sur->steps : 0;
   out->judge_steps = s->sur ? s->sur->judge_steps : 0;
   out->judge_flagged = cnt[0];
   out->range_flagged = cnt[1];
   out->fallback = cnt[2];
+  out->fallback_total = (int64_t)total;
   out->n_columns = s->grid->h.ne;
   return DC_OK;
 }

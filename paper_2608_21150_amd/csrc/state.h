@@ -48,7 +48,8 @@ struct dc_state {
   void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
   double *wstar, *wtmp, *fe, *tau, *diag_part, *diag_out;
   // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
-  // held viscosity [K][es], judge and range flags [es], counters [4]
+  // held viscosity [K][es], judge and range flags [es], counters (4 int,
+  // then one 64-bit)
   dc::SurCtx* sur = nullptr;
   void* sur_tmlp = nullptr;
   void* sur_nu = nullptr;

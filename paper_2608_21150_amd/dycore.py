@@ -76,7 +76,8 @@ class TrainCfg(ctypes.Structure):
 
 class SurrogateInfo(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("judge_steps", ctypes.c_int64), ("judge_flagged", ctypes.c_int64),
-                ("range_flagged", ctypes.c_int64), ("fallback", ctypes.c_int64), ("n_columns", ctypes.c_int64)]
+                ("range_flagged", ctypes.c_int64), ("fallback", ctypes.c_int64), ("fallback_total", ctypes.c_int64),
+                ("n_columns", ctypes.c_int64)]
 
 
 class KernelStat(ctypes.Structure):

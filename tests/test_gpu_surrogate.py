@@ -174,6 +174,7 @@ def test_threshold_zero_equals_plain_run(precision):
     info = sur.surrogate_stats()
     assert info["steps"] == 5 and info["judge_steps"] == 2
     assert info["judge_flagged"] == G.info["n_edges"] and info["fallback"] == G.info["n_edges"]
+    assert info["fallback_total"] == 3 * G.info["n_edges"]
     assert sur.diag()["fallback_fraction"] == 1.0
     sur.close()
     plain.close()
@@ -214,6 +215,32 @@ def test_out_of_range_column_falls_back():
     plain.close()
     net.close()
     G.close()
+
+
+def test_fit_norm_keeps_tiny_scales():
+    """Feature scales span many orders of magnitude (div L1 ~ 1e-17 on a
+    global grid): each gets its own scale, flow features and the target a
+    zero mean and the symmetric range."""
+    rng = np.random.default_rng(21)
+    n = 5000
+    scales = 10.0 ** np.linspace(-24, 2, 19)
+    h = rng.normal(size=(19, n)) * scales[:, None]
+    h[16:18] = 1.0 + 0.1 * rng.normal(size=(2, n))  # geometric ratios
+    buf = torch.tensor(h, dtype=torch.float32, device="cuda")
+    net = D.Mlp(0)
+    net.fit_norm(buf, n)
+    nrm = net.norm()
+    hf = h.astype(np.float32).astype(np.float64)
+    for i in range(16):
+        rms = np.sqrt(np.mean(hf[i] ** 2))
+        assert nrm["mean"][i] == 0.0 and abs(nrm["std"][i] / rms - 1) < 1e-5, i
+        amax = np.max(np.abs(hf[i]))
+        assert nrm["min"][i] == np.float32(-amax) and nrm["max"][i] == np.float32(amax), i
+    for i in (16, 17):
+        assert abs(nrm["mean"][i] - hf[i].mean()) < 1e-6 and abs(nrm["std"][i] / hf[i].std() - 1) < 1e-4
+        assert nrm["min"][i] == np.float32(hf[i].min()) and nrm["max"][i] == np.float32(hf[i].max())
+    assert abs(nrm["target_std"] / np.sqrt(np.mean(hf[18] ** 2)) - 1) < 1e-5
+    net.close()
 
 
 def test_training_reduces_loss_and_fits():

@@ -81,9 +81,13 @@ def test_features_definitions():
     vt = op.recon_vt(g, vn)
     assert f[k, e, 0] == vn[k, e] and f[k, e, 1] == vt[k, e]
     D = op.div(g, vn)
-    assert f[k, e, 3] == D[k, g.e2c[e, 1]]
+    c0, c1 = g.e2c[e]
+    assert f[k, e, 2] == 0.5 * (D[k, c0] + D[k, c1]) and f[k, e, 3] == (D[k, c1] - D[k, c0]) / g.d_e[e]
     z = op.curl(g, vn)
-    assert f[k, e, 5] == z[k, g.e2c2v[e, 1]] and f[k, e, 15] == z[k, g.e2c2v[e, 3]]
+    v0, v1, v2, v3 = g.e2c2v[e]
+    assert f[k, e, 5] == (z[k, v1] - z[k, v0]) / g.l_e[e] and f[k, e, 14] == 0.5 * (z[k, v2] + z[k, v3])
+    # the tangent-ordered end vertices are e2c2v[:, :2], the same as e2v
+    assert np.array_equal(g.e2c2v[:, :2], g.e2v)
     assert np.allclose(f[0, :, 16].mean(), 1.0) and np.allclose(f[0, :, 17].mean(), 1.0)
     # odd in the flow: flipping vn flips the 16 flow features, keeps geometry
     f2 = M.features(g, -vn)
@@ -105,11 +109,15 @@ def test_features_of_a_solid_body_rotation():
     vn = np.einsum("ej,ej->e", u, g.nrm)[None, :]
     f = M.features(g, vn)
     scale_d = om  # natural size of the divergence and vorticity
-    assert np.max(np.abs(f[0, :, 2:4])) < 2e-2 * scale_d  # discretely almost divergence-free
+    assert np.max(np.abs(f[0, :, 2])) < 2e-2 * scale_d  # discretely almost divergence-free
     lat = g.xv[:, 2]
     z_ref = 2.0 * om * lat  # curl of a rigid rotation
     zz = f[0, :, 4]
-    assert np.max(np.abs(zz - z_ref[g.e2c2v[:, 0]])) < 2e-2 * 2 * om
+    z_mid = 0.5 * (z_ref[g.e2c2v[:, 0]] + z_ref[g.e2c2v[:, 1]])
+    assert np.max(np.abs(zz - z_mid)) < 2e-2 * 2 * om
+    # and the along-edge vorticity gradient is that of 2 Omega sin(lat)
+    dz_ref = (z_ref[g.e2c2v[:, 1]] - z_ref[g.e2c2v[:, 0]]) / g.l_e
+    assert np.max(np.abs(f[0, :, 5] - dz_ref)) < 0.1 * np.max(np.abs(dz_ref))
     # deformation of a rigid rotation vanishes (the least-squares vertex
     # vectors leave a discretisation error, largest near the 12 pentagons),
     # while each shear derivative is of the size of the rotation rate: a sign
@@ -122,9 +130,10 @@ def test_features_of_a_solid_body_rotation():
 
 
 def test_features_determine_the_plain_tendency():
-    """The linear part of the diffusion tendency is an exact function of
-    features 2..9 and the geometry: -k4 A_e^2 / dt (grad divL1 - gradt curlL1)
-    + nu L1, with L1 = (D1 - D0)/d - (z1 - z0)/l, nu from features 10..13."""
+    """The plain diffusion tendency is an exact function of the features and
+    the geometry: nu L1 - k4 A_e^2 L2 / dt with L1 = f3 - f5 (grad D -
+    gradt Z), L2 = f7 - f9 (grad div L1 - gradt curl L1) and nu from the
+    deformation of features 10..13."""
     from oracle import dycore as dy
     from oracle.constants import default_params
     from oracle.grid import Grid
@@ -137,8 +146,8 @@ def test_features_determine_the_plain_tendency():
     dt = 300.0
     f = M.features(g, S["vn"])
     T = M.diffusion_tendency(g, p, S, dt, dy.diffusion)
-    L1 = (f[..., 3] - f[..., 2]) / g.d_e - (f[..., 5] - f[..., 4]) / g.l_e
-    L2 = (f[..., 7] - f[..., 6]) / g.d_e - (f[..., 9] - f[..., 8]) / g.l_e
+    L1 = f[..., 3] - f[..., 5]
+    L2 = f[..., 7] - f[..., 9]
     deform = np.hypot(f[..., 12] - f[..., 11], f[..., 13] + f[..., 10])
     nu = np.minimum(p["smag_cs"] * g.a_e * deform, g.a_e / (p["smag_cap"] * dt))
     T_f = nu * L1 - p["hdiff_k4"] * g.a_e**2 * L2 / dt
