@@ -54,6 +54,98 @@ def step_algorithmic_bytes(C, E, K, nsub, r):
     return nsub * (pred + corr) + diff
 
 
+# kernels of the step as rocprofv3 names them -> the ids used above
+_BODY_IDS = {("BVc", "false"): "vort_ke_pred", ("BVc", "true"): "vort_ke_corr",
+             ("BEdge", "false"): "edge_pred", ("BEdge", "true"): "edge_corr",
+             ("BCol", "false"): "column_pred", ("BCol", "true"): "column_corr",
+             ("BDvert", None): "diff_vertex", ("BDiv", None): "diff_div", ("BDedge1", None): "diff_edge1",
+             ("BDcv2", None): "diff_cell_vertex2", ("BDedge2", None): "diff_edge2"}
+
+
+def kernel_id(name):
+    """Step-kernel id of a rocprofv3 kernel name (None for other kernels)."""
+    import re
+
+    m = re.search(r"k_one<dc::bodies::(B\w+)<(?:double|float)(?:, (true|false))?", name)
+    if not m:
+        return None
+    return _BODY_IDS.get((m.group(1), m.group(2)))
+
+
+def sources_sha256():
+    """Hash of the kernel sources: counter figures taken with other sources are stale."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2608_21150_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def summarize_profile(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, out, command, workload, precision):
+    """Markdown summary of a rocprofv3 kernel-trace run and two counter runs
+    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), scaled by what the same
+    counters read for a 1 GiB device copy; the last line carries the scaled
+    bytes per launch of every step kernel and the kernel-source hash."""
+    import collections
+    import csv
+
+    def short(n):
+        return n.replace("dc::bodies::", "").replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+
+    def counters(d):
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in agg.items()}
+
+    rows = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
+    F, W, cF, cW = counters(fetch_dir), counters(write_dir), counters(cfetch_dir), counters(cwrite_dir)
+    copy = [k for k in cF if "copyBuffer" in k][0]
+    kib = 1024 * 1024  # the copy moves 1 GiB each way
+    sf, sw = kib / cF[copy], kib / cW[[k for k in cW if "copyBuffer" in k][0]]
+    lines = [f"command: `{command}`", "",
+             f"counter calibration (`python bench.py --calibrate-copy 1024`, a 1 GiB device-to-device copy): "
+             f"FETCH_SIZE reads {cF[copy]:.0f} KiB and WRITE_SIZE {cW[[k for k in cW if 'copyBuffer' in k][0]]:.0f} "
+             f"KiB per {kib} KiB moved -> scale fetch x{sf:.3f}, write x{sw:.3f}", "",
+             "| kernel | id | calls | avg us | share % | FETCH KiB raw | WRITE KiB raw | HBM MB/launch (scaled) |",
+             "|---|---|---|---|---|---|---|---|"]
+    per = {}
+    for r in rows:
+        name = r["Name"]
+        f, w = F.get(name), W.get(name)
+        mb = (f * sf + w * sw) * 1024 / 1e6 if f is not None and w is not None else None
+        kid = kernel_id(name)
+        if kid and mb is not None:
+            per[kid] = {"bytes": mb * 1e6, "avg_us": float(r["AverageNs"]) / 1e3}
+        lines.append(f"| {short(name)[:90]} | {kid or '-'} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} | {f if f is None else round(f, 1)} | "
+                     f"{w if w is None else round(w, 1)} | {'-' if mb is None else round(mb, 1)} |")
+    meta = {"workload": workload, "precision": precision, "sources_sha256": sources_sha256(),
+            "fetch_scale": sf, "write_scale": sw, "kernels": per}
+    lines += ["", "<!-- traffic " + json.dumps(meta) + " -->"]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def profiled_traffic(workload, precision, kid):
+    """HBM bytes per launch of kernel kid from the committed counter summary
+    of this workload, or None if there is none or its sources differ."""
+    path = os.path.join(ROOT, "profiles", f"step_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("<!-- traffic "):
+            meta = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+            if meta.get("sources_sha256") != sources_sha256() or kid not in meta["kernels"]:
+                return None
+            return meta["kernels"][kid]["bytes"]
+    return None
+
+
 def cpu_baseline(spec, g0, S, vert, budget_s=25.0):
     """The oracle, as it stands, on one host core for a bounded sample."""
     import numpy as np
@@ -272,7 +364,15 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write a profile summary from rocprofv3 output folders and exit")
+    ap.add_argument("--profile-out", default=None)
+    ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(*args.summarize_profile, args.profile_out, args.profile_command, args.workload,
+                          args.precision)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -346,7 +446,8 @@ def main():
     dk = kernels[dom]
     achieved = dk["GBps"]
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": profiled_traffic(args.workload, args.precision, dom),
             "bytes_per_launch": kb[dom], "avg_launch_us": round(dk["avg_us"], 2)}
     b_step = step_algorithmic_bytes(C, E, K, spec["nsub"], r)
     line = {
