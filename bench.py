@@ -25,15 +25,21 @@ FIELDS = ("vn", "w", "rho", "exner", "theta_v")
 def kernel_bytes(C, E, V, K, r):
     """Algorithmic bytes of one launch of each kernel: every array the kernel
     reads or writes counted once per (entity, level); r = bytes of vn and of
-    the horizontal intermediates (8 FP64, 4 mixed); cell prognostics are 8."""
-    KE, KV, KC, K1C = K * E, K * V, K * C, (K + 1) * C
+    the horizontal intermediates (8 FP64, 4 mixed); cell prognostics are 8.
+    gw is the edge term of the horizontal advection of w ([K+1][E], r bytes),
+    tw0 the substep-start T_w ([K+1][C], 8 bytes)."""
+    KE, KV, KC, K1C, K1E = K * E, K * V, K * C, (K + 1) * C, (K + 1) * E
     return {
         "vort_ke_pred": r * KE + r * (KV + KC),
-        "edge_pred": r * KE + r * KV + r * KC + 8 * K1C + 8 * 2 * KC + r * 2 * KE,
-        "column_pred": 2 * r * KE + 8 * K1C + 8 * 3 * KC + 8 * K1C,
+        # reads vn, zeta, K_c, w, exner, theta; writes T_vn0, vn*, gw
+        "edge_pred": r * KE + r * KV + r * KC + 8 * K1C + 8 * 2 * KC + r * 3 * KE,
+        # reads gw, vn*, w, rho, exner, theta; writes w*, tw0
+        "column_pred": r * K1E + r * KE + 8 * K1C + 8 * 3 * KC + 8 * 2 * K1C,
         "vort_ke_corr": r * KE + r * (KV + 2 * KC),
-        "edge_corr": r * 3 * KE + r * KV + r * 2 * KC + 8 * K1C + 8 * 2 * KC + r * KE,
-        "column_corr": 3 * r * KE + 2 * 8 * K1C + 8 * 3 * KC + 8 * (K1C + 3 * KC),
+        # reads vn*, T_vn0, vn, zeta, K_c, D2, w*, exner, theta; writes vn', gw
+        "edge_corr": r * 3 * KE + r * KV + r * 2 * KC + 8 * K1C + 8 * 2 * KC + r * 2 * KE,
+        # reads gw, vn', w, w*, tw0, rho, exner, theta; writes w, rho, exner, theta
+        "column_corr": r * K1E + r * KE + 8 * 3 * K1C + 8 * 3 * KC + 8 * (K1C + 3 * KC),
         "diff_vertex": r * KE + r * 4 * KV,
         "diff_div": r * KE + r * KC,
         "diff_edge1": r * KC + r * 4 * KV + r * 2 * KE,

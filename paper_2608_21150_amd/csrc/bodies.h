@@ -181,12 +181,14 @@ struct BEdge {
     R* vout;
     const R* vn_now;
     const R* d2;
+    R* gw;  // out: l_e vn_ie (w_c1 - w_c0) at the half levels 1..K-1
     StepCoef cf;
     int kb;
   };
   static constexpr int kThreads = 256;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const R* __restrict__ vn = args.vn;
+    R* __restrict__ gw = args.gw;
     const R* __restrict__ zeta = args.zeta;
     const R* __restrict__ kc = args.kc;
     const double* __restrict__ w = args.w;
@@ -206,6 +208,7 @@ struct BEdge {
     const double invd = g.invd[e];
     const R invd_r = (R)invd;
     const R fe = (R)g.fe[e];
+    const R le = (R)(1.0 / g.invl[e]);
     VtStencil<R> vts;
     vts.load(g, e);
     const double* idzf = vt_row(g, VT_IDZF);
@@ -225,6 +228,9 @@ struct BEdge {
       const double* wa = w + (size_t)j * g.cs;
       const double* wb = wa + g.cs;
       const R wef = (R)(0.5 * (0.5 * (wa[c0] + wa[c1]) + 0.5 * (wb[c0] + wb[c1])));
+      // this edge's share of the horizontal advection of w at half level j:
+      // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
+      if (j > 0) gw[re] = le * ie_top * (R)(wa[c1] - wa[c0]);
       const R vt = vts.apply(vn + (size_t)j * g.es, e);
       const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
       const size_t rc = (size_t)j * g.cs;
@@ -262,28 +268,21 @@ struct BEdge {
 template <typename R>
 struct ColArgs {
   const double *w, *rho, *ex, *th;  // state at the start of the substep
-  const R* vn;                       // vn at the start of the substep (T_w)
+  const R* gw;                       // edge terms of T_w of this pass (from the edge kernel)
   const R* vnf;                      // vn of the mass fluxes (vn* / new vn)
-  const R* vns;                      // corrector: predicted vn* (T_w*)
+  double* tw0;                       // T_w at the substep start: written (predictor), read (corrector)
   const double* ws;                  // corrector: predicted w* (T_w*)
   double *w_out, *rho_out, *ex_out, *th_out;
 };
 
-// T_w at half level k (1 <= k <= K-1) of column c from vn and w (w_up, w_k,
-// w_dn: the column's own w at half levels k-1, k, k+1).
+// T_w at half level k (1 <= k <= K-1) of column c: horizontal part from the
+// three edge terms l_e vn_ie (w_c1 - w_c0) of the cell (gw, over A_c), vertical
+// part from the column's own w at half levels k-1, k, k+1 (w_up, w_k, w_dn).
 template <typename R>
-__device__ __forceinline__ double col_tw(const DevGrid& g, const R* __restrict__ vn, const double* __restrict__ w,
-                                         double w_up, double w_k, double w_dn, int k, const int* ie, const int* nb,
-                                         const R* kd) {
-  const R* va = vn + (size_t)(k - 1) * g.es;
-  const R* vb = vn + (size_t)k * g.es;
-  const double* wr = w + (size_t)k * g.cs;
-  R hs = R(0);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const R vie = R(0.5) * (va[ie[i]] + vb[ie[i]]);
-    hs += kd[i] * vie * (R)(wr[nb[i]] - w_k);
-  }
+__device__ __forceinline__ double col_tw(const DevGrid& g, const R* __restrict__ gw, double w_up, double w_k,
+                                         double w_dn, int k, const int* ie, R inv_area) {
+  const R* gr = gw + (size_t)k * g.es;
+  const R hs = (gr[ie[0]] + gr[ie[1]] + gr[ie[2]]) * inv_area;
   const double dwdz = (w_up - w_dn) * vt_row(g, VT_IDZC2)[k];
   return (double)(R(-0.5) * hs - (R)(w_k * dwdz));
 }
@@ -349,14 +348,13 @@ struct BCol {
     const double eta = cf.eta, dtau = cf.dtau, cpd = cf.cpd, oneme = 1.0 - eta;
     int ie[3], nb[3];
     double kd[3];
-    R kdr[3];
   #pragma unroll
     for (int q = 0; q < 3; ++q) {
       ie[q] = g.c2e[q * cs + c];
       nb[q] = g.c2e2c[q * cs + c];
       kd[q] = g.kdiv[q * cs + c];
-      kdr[q] = (R)kd[q];
     }
+    const R inv_area = (R)(1.0 / g.area[c]);
 
     // ---- forward sweep over levels h..h+n: explicit parts, rows, down sweep ----
     double cpv[LM], dpv[LM], lpv[LM];
@@ -420,8 +418,13 @@ struct BCol {
         dxxv[i] = dxx;
         if (i >= 1) {
           // row of half level j, then one step of the down sweep
-          double tw = col_tw<R>(g, a.vn, a.w, w_up, cur.w, nx.w, j, ie, nb, kdr);
-          if (CORR) tw = cf.a0 * tw + cf.a1 * col_tw<R>(g, a.vns, a.ws, ws_up, cur.ws, nx.ws, j, ie, nb, kdr);
+          double tw;
+          if (CORR) {
+            tw = cf.a0 * a.tw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(g, a.gw, ws_up, cur.ws, nx.ws, j, ie, inv_area);
+          } else {
+            tw = col_tw<R>(g, a.gw, w_up, cur.w, nx.w, j, ie, inv_area);
+            if (ok) a.tw0[(size_t)j * cs + c] = tw;
+          }
           const double wx = cur.w + dtau * (tw - cpd * cur.zth);
           const double A = -cur.gam * beta_p * (eta * atil_p);
           const double B = 1.0 + cur.gam * (eta * cur.atil) * (beta_p + beta);
@@ -1004,11 +1007,11 @@ SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& 
   const int P = col_chunks_lm(g.K, &lm);
   const int ncb = cdiv(g.nc, T[T_VC].threads);
   s.vc_p = {b.vn, b.zeta, b.kc, nullptr, ncb, T[T_VC].kb};
-  s.e_p = {b.vn, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, c, T[T_EDGE].kb};
-  s.c_p = {{b.w, b.rho, b.ex, b.th, b.vn, b.vns, nullptr, nullptr, b.ws, nullptr, nullptr, nullptr}, c, P};
+  s.e_p = {b.vn, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
+  s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, nullptr, b.ws, nullptr, nullptr, nullptr}, c, P};
   s.vc_c = {b.vns, b.zeta, b.kc, b.d2, ncb, T[T_VC].kb};
-  s.e_c = {b.vns, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, c, T[T_EDGE].kb};
-  s.c_c = {{b.w, b.rho, b.ex, b.th, b.vn, b.vn_out, b.vns, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, P};
+  s.e_c = {b.vns, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
+  s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, P};
   return s;
 }
 

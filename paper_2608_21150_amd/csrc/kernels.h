@@ -86,6 +86,8 @@ struct Bufs {
   // workspace
   R *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
   double *ws, *wtmp;
+  R* gw;        // [K+1][es] edge terms of the horizontal advection of w
+  double* tw0;  // [K+1][cs] T_w at the substep start (predictor -> corrector)
   // outputs of the corrector
   R* vn_out;
   double *w_out, *rho_out, *ex_out, *th_out;

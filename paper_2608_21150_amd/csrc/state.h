@@ -45,8 +45,8 @@ struct dc_state {
   // workspace carve-up
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
-  double *wstar, *wtmp, *fe, *tau, *diag_part, *diag_out;
+  void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv, *gw;
+  double *wstar, *wtmp, *tw0, *fe, *tau, *diag_part, *diag_out;
   // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
   // held viscosity [K][es], judge and range flags [es], counters (4 int,
   // then one 64-bit)
@@ -101,6 +101,8 @@ Bufs<R> substep_bufs(const dc_state* s, int cur_idx, bool w_to_staging) {
   b.vv = static_cast<R*>(s->vv);
   b.ws = s->wstar;
   b.wtmp = s->wtmp;
+  b.gw = static_cast<R*>(s->gw);
+  b.tw0 = s->tw0;
   b.vn_out = static_cast<R*>(nxt.vn);
   b.w_out = w_to_staging ? s->wtmp : static_cast<double*>(nxt.w);
   b.rho_out = static_cast<double*>(nxt.rho);
