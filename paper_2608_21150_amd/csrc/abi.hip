@@ -46,7 +46,7 @@ dc_status fail(dc_status code, const std::string& msg) {
 size_t elem_size(dc_precision prec) { return prec == DC_PREC_MIXED ? sizeof(float) : sizeof(double); }
 
 struct Layout {
-  size_t vt, tvn0, vns, kc, d2, zeta, vv, gw, wstar, wtmp, tw0, fe, tau, dpart, dout;
+  size_t vt, tvn0, vns, kc, d2, zeta, vv, gw, dvn, wstar, wtmp, tw0, fe, tau, dpart, dout;
   size_t s_tmlp, s_nu, s_fj, s_fr, s_cnt;  // surrogate mode only
   size_t total;
 };
@@ -69,6 +69,7 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff)
   L.zeta = take(K * h.vs * r);
   L.vv = take(3 * K * h.vs * r);
   L.gw = take(K1 * h.es * r);
+  L.dvn = take(K * h.cs * r);
   L.wstar = take(K1 * h.cs * 8);
   L.wtmp = take(K1 * h.cs * 8);
   L.tw0 = take(K1 * h.cs * 8);
@@ -368,6 +369,7 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->zeta = w + L.zeta;
   s->vv = w + L.vv;
   s->gw = w + L.gw;
+  s->dvn = w + L.dvn;
   s->wstar = reinterpret_cast<double*>(w + L.wstar);
   s->wtmp = reinterpret_cast<double*>(w + L.wtmp);
   s->tw0 = reinterpret_cast<double*>(w + L.tw0);

@@ -72,7 +72,8 @@ struct VtStencil {
 //  vertices: relative vorticity zeta_v = (1/A_v) sum sig d_e vn_e
 //  cells:    kinetic energy K_c = mean over the 3 edges of (vn^2 + vt^2)/2,
 //            vt reconstructed in place; in the corrector also the
-//            divergence-damping field D2 = laps(div vn).
+//            divergence-damping field D2 = laps(D) from D = div vn*, which
+//            the predictor's column kernel stored.
 // ---------------------------------------------------------------------------
 template <typename R, bool CORR>
 struct BVc {
@@ -81,6 +82,7 @@ struct BVc {
     R* zeta;
     R* kc;
     R* d2;
+    const R* dv;  // corrector: D = div vn*
     int ncb;
     int kb;
   };
@@ -115,27 +117,17 @@ struct BVc {
     const int c = bx * blockDim.x + threadIdx.x;
     if (c >= g.nc) return;
     int ie[3], nb[3];
-    R kd[3];
     VtStencil<R> vts[3];
   #pragma unroll
     for (int i = 0; i < 3; ++i) {
       ie[i] = g.c2e[i * g.cs + c];
       nb[i] = g.c2e2c[i * g.cs + c];
-      kd[i] = (R)g.kdiv[i * g.cs + c];
       vts[i].load(g, ie[i]);
     }
-    int ie2[3][3];
-    R kd2[3][3], kl[3];
+    R kl[3];
     if (CORR) {
   #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        kl[i] = (R)g.klap[i * g.cs + c];
-  #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          ie2[i][m] = g.c2e[m * g.cs + nb[i]];
-          kd2[i][m] = (R)g.kdiv[m * g.cs + nb[i]];
-        }
-      }
+      for (int i = 0; i < 3; ++i) kl[i] = (R)g.klap[i * g.cs + c];
     }
     for (int k = k0; k < k1; ++k) {
       const R* vrow = vn + (size_t)k * g.es;
@@ -147,13 +139,11 @@ struct BVc {
       }
       kc[(size_t)k * g.cs + c] = ke / R(3);
       if (CORR) {
-        const R dc = kd[0] * vrow[ie[0]] + kd[1] * vrow[ie[1]] + kd[2] * vrow[ie[2]];
+        const R* drow = args.dv + (size_t)k * g.cs;
+        const R dc = drow[c];
         R acc = R(0);
   #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const R dn = kd2[i][0] * vrow[ie2[i][0]] + kd2[i][1] * vrow[ie2[i][1]] + kd2[i][2] * vrow[ie2[i][2]];
-          acc += kl[i] * (dn - dc);
-        }
+        for (int i = 0; i < 3; ++i) acc += kl[i] * (drow[nb[i]] - dc);
         d2[(size_t)k * g.cs + c] = acc;
       }
     }
@@ -271,6 +261,7 @@ struct ColArgs {
   const R* gw;                       // edge terms of T_w of this pass (from the edge kernel)
   const R* vnf;                      // vn of the mass fluxes (vn* / new vn)
   double* tw0;                       // T_w at the substep start: written (predictor), read (corrector)
+  R* dv_out;                         // predictor: D = div vn* at the full levels
   const double* ws;                  // corrector: predicted w* (T_w*)
   double *w_out, *rho_out, *ex_out, *th_out;
 };
@@ -399,15 +390,21 @@ struct BCol {
           const R* vr = a.vnf + (size_t)j * g.es;
           const double* rr = a.rho + (size_t)j * cs;
           const double* tr = a.th + (size_t)j * cs;
+          R vq[3];
   #pragma unroll
           for (int q = 0; q < 3; ++q) {
+            vq[q] = vr[ie[q]];
             const R rho_e = (R)(0.5 * (cur.rho + rr[nb[q]]));
             const R th_e = (R)(0.5 * (cur.th + tr[nb[q]]));
-            const R fm = rho_e * vr[ie[q]];
+            const R fm = rho_e * vq[q];
             const R ft = fm * th_e;
             dm += kd[q] * (double)fm;
             dth += kd[q] * (double)ft;
           }
+          // predictor: divergence of vn* for the corrector's damping (each
+          // full level is stored by the chunk that owns it)
+          if (!CORR && ok && (i >= 1 || p == 0))
+            a.dv_out[(size_t)j * cs + c] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
         }
         const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
         const double beta = b * idzf[j];
@@ -430,15 +427,18 @@ struct BCol {
           const double B = 1.0 + cur.gam * (eta * cur.atil) * (beta_p + beta);
           const double C = -cur.gam * beta * (eta * nx.atil);
           const double rhs = wx - cur.gam * (e_p - e_c);
+          // one reciprocal per row: the pivots are >= 1, so multiplying by
+          // it loses nothing against three divisions
           if (i == 1) {
-            cpv[0] = C / B;
-            dpv[0] = rhs / B;
-            lpv[0] = A / B;
+            const double r = 1.0 / B;
+            cpv[0] = C * r;
+            dpv[0] = rhs * r;
+            lpv[0] = A * r;
           } else {
-            const double den = B - A * cpv[i - 2];
-            cpv[i - 1] = C / den;
-            dpv[i - 1] = (rhs - A * dpv[i - 2]) / den;
-            lpv[i - 1] = -A * lpv[i - 2] / den;
+            const double r = 1.0 / (B - A * cpv[i - 2]);
+            cpv[i - 1] = C * r;
+            dpv[i - 1] = (rhs - A * dpv[i - 2]) * r;
+            lpv[i - 1] = -A * lpv[i - 2] * r;
           }
         }
         beta_p = beta;
@@ -569,7 +569,7 @@ struct BCol {
               const size_t r = (size_t)j * cs + c;
               a.rho_out[r] = rho_new;
               a.ex_out[r] = lv.ex + dex;
-              a.th_out[r] = lv.th + (lv.rho * lv.th * cf.cvd_rd * dex / lv.ex - lv.th * drho) / rho_new;
+              a.th_out[r] = lv.th + lv.th * (lv.rho * cf.cvd_rd * dex - drho * lv.ex) / (lv.ex * rho_new);
             }
           }
           w0 = w1;
@@ -1006,12 +1006,12 @@ SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& 
   int lm;
   const int P = col_chunks_lm(g.K, &lm);
   const int ncb = cdiv(g.nc, T[T_VC].threads);
-  s.vc_p = {b.vn, b.zeta, b.kc, nullptr, ncb, T[T_VC].kb};
+  s.vc_p = {b.vn, b.zeta, b.kc, nullptr, nullptr, ncb, T[T_VC].kb};
   s.e_p = {b.vn, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
-  s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, nullptr, b.ws, nullptr, nullptr, nullptr}, c, P};
-  s.vc_c = {b.vns, b.zeta, b.kc, b.d2, ncb, T[T_VC].kb};
+  s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr}, c, P};
+  s.vc_c = {b.vns, b.zeta, b.kc, b.d2, b.dvn, ncb, T[T_VC].kb};
   s.e_c = {b.vns, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
-  s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, P};
+  s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, P};
   return s;
 }
 

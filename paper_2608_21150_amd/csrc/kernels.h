@@ -87,6 +87,7 @@ struct Bufs {
   R *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
   double *ws, *wtmp;
   R* gw;        // [K+1][es] edge terms of the horizontal advection of w
+  R* dvn;       // [K][cs] div vn* (predictor column kernel -> corrector damping)
   double* tw0;  // [K+1][cs] T_w at the substep start (predictor -> corrector)
   // outputs of the corrector
   R* vn_out;

@@ -45,7 +45,7 @@ struct dc_state {
   // workspace carve-up
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv, *gw;
+  void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv, *gw, *dvn;
   double *wstar, *wtmp, *tw0, *fe, *tau, *diag_part, *diag_out;
   // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
   // held viscosity [K][es], judge and range flags [es], counters (4 int,
@@ -102,6 +102,7 @@ Bufs<R> substep_bufs(const dc_state* s, int cur_idx, bool w_to_staging) {
   b.ws = s->wstar;
   b.wtmp = s->wtmp;
   b.gw = static_cast<R*>(s->gw);
+  b.dvn = static_cast<R*>(s->dvn);
   b.tw0 = s->tw0;
   b.vn_out = static_cast<R*>(nxt.vn);
   b.w_out = w_to_staging ? s->wtmp : static_cast<double*>(nxt.w);
