@@ -64,7 +64,7 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff)
   L.vt = take(K * h.es * r);
   L.tvn0 = take(K * h.es * r);
   L.vns = take(K * h.es * r);
-  L.kc = take(K * h.cs * r);
+  L.kc = take(K * std::max(h.es, h.cs) * r);  // K_e [K][es] in substeps, div vn [K][cs] in diffusion
   L.d2 = take(K1 * h.cs * r);
   L.zeta = take(K * h.vs * r);
   L.vv = take(3 * K * h.vs * r);

@@ -68,35 +68,51 @@ struct VtStencil {
 };
 
 // ---------------------------------------------------------------------------
-// vertex + cell pass (one launch, blocks [0, ncb) are cells):
+// edge + vertex (+ cell) pass, one launch: blocks [0, neb) are edges, the
+// next nvb blocks vertices, and in the corrector the rest cells.
+//  edges:    tangential wind vt (Perot) and kinetic energy K_e = (vn^2 + vt^2)/2
 //  vertices: relative vorticity zeta_v = (1/A_v) sum sig d_e vn_e
-//  cells:    kinetic energy K_c = mean over the 3 edges of (vn^2 + vt^2)/2,
-//            vt reconstructed in place; in the corrector also the
-//            divergence-damping field D2 = laps(D) from D = div vn*, which
-//            the predictor's column kernel stored.
+//  cells:    (corrector) the divergence-damping field D2 = laps(D) from
+//            D = div vn*, which the predictor's column kernel stored.
+// The cell kinetic energy K_c = mean of K_e over the cell's edges is not
+// stored: the edge kernel forms grad K_c from K_e of the rhombus edges.
 // ---------------------------------------------------------------------------
 template <typename R, bool CORR>
 struct BVc {
   struct Args {
     const R* vn;
     R* zeta;
-    R* kc;
+    R* vt;
+    R* ke;
     R* d2;
     const R* dv;  // corrector: D = div vn*
-    int ncb;
+    int neb, nvb;
     int kb;
   };
   static constexpr int kThreads = 256;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const R* __restrict__ vn = args.vn;
-    R* __restrict__ zeta = args.zeta;
-    R* __restrict__ kc = args.kc;
-    R* __restrict__ d2 = args.d2;
-    const int ncb = args.ncb;
     const int kb = args.kb;
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
-    if (bx >= ncb) {
-      const int v = (bx - ncb) * blockDim.x + threadIdx.x;
+    if (bx < args.neb) {
+      const int e = bx * blockDim.x + threadIdx.x;
+      if (e >= g.ne) return;
+      R* __restrict__ vt = args.vt;
+      R* __restrict__ ke = args.ke;
+      VtStencil<R> vts;
+      vts.load(g, e);
+      for (int k = k0; k < k1; ++k) {
+        const R* row = vn + (size_t)k * g.es;
+        const R a = row[e], b = vts.apply(row, e);
+        const size_t r = (size_t)k * g.es + e;
+        vt[r] = b;
+        ke[r] = R(0.5) * (a * a + b * b);
+      }
+      return;
+    }
+    if (bx < args.neb + args.nvb) {
+      R* __restrict__ zeta = args.zeta;
+      const int v = (bx - args.neb) * blockDim.x + threadIdx.x;
       if (v >= g.nv) return;
       int idx[6];
       R cf[6];
@@ -114,31 +130,18 @@ struct BVc {
       }
       return;
     }
-    const int c = bx * blockDim.x + threadIdx.x;
-    if (c >= g.nc) return;
-    int ie[3], nb[3];
-    VtStencil<R> vts[3];
-  #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      ie[i] = g.c2e[i * g.cs + c];
-      nb[i] = g.c2e2c[i * g.cs + c];
-      vts[i].load(g, ie[i]);
-    }
-    R kl[3];
     if (CORR) {
-  #pragma unroll
-      for (int i = 0; i < 3; ++i) kl[i] = (R)g.klap[i * g.cs + c];
-    }
-    for (int k = k0; k < k1; ++k) {
-      const R* vrow = vn + (size_t)k * g.es;
-      R ke = R(0);
+      R* __restrict__ d2 = args.d2;
+      const int c = (bx - args.neb - args.nvb) * blockDim.x + threadIdx.x;
+      if (c >= g.nc) return;
+      int nb[3];
+      R kl[3];
   #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const R a = vrow[ie[i]], b = vts[i].apply(vrow, ie[i]);
-        ke += R(0.5) * (a * a + b * b);
+        nb[i] = g.c2e2c[i * g.cs + c];
+        kl[i] = (R)g.klap[i * g.cs + c];
       }
-      kc[(size_t)k * g.cs + c] = ke / R(3);
-      if (CORR) {
+      for (int k = k0; k < k1; ++k) {
         const R* drow = args.dv + (size_t)k * g.cs;
         const R dc = drow[c];
         R acc = R(0);
@@ -163,7 +166,8 @@ struct BEdge {
   struct Args {
     const R* vn;
     const R* zeta;
-    const R* kc;
+    const R* ke;  // K_e of this pass's vn
+    const R* vt;  // vt of this pass's vn
     const double* w;
     const double* ex;
     const double* th;
@@ -180,7 +184,8 @@ struct BEdge {
     const R* __restrict__ vn = args.vn;
     R* __restrict__ gw = args.gw;
     const R* __restrict__ zeta = args.zeta;
-    const R* __restrict__ kc = args.kc;
+    const R* __restrict__ ke = args.ke;
+    const R* __restrict__ vtf = args.vt;
     const double* __restrict__ w = args.w;
     const double* __restrict__ ex = args.ex;
     const double* __restrict__ th = args.th;
@@ -199,8 +204,12 @@ struct BEdge {
     const R invd_r = (R)invd;
     const R fe = (R)g.fe[e];
     const R le = (R)(1.0 / g.invl[e]);
-    VtStencil<R> vts;
-    vts.load(g, e);
+    // the other two edges of c0, then of c1: K_c1 - K_c0 is a third of the
+    // difference of their kinetic energies (the edge's own K_e cancels)
+    int rh[4];
+  #pragma unroll
+    for (int s = 0; s < 4; ++s) rh[s] = g.e2c2e[s * g.es + e];
+    const R third = R(1) / R(3);
     const double* idzf = vt_row(g, VT_IDZF);
     const double* exref = vt_row(g, VT_EXREF);
     const int k0 = by * kb, k1 = min(K, k0 + kb);
@@ -213,15 +222,15 @@ struct BEdge {
       const R ie_bot = j < K - 1 ? R(0.5) * (vj + vdn) : vj;
       const R* zr = zeta + (size_t)j * g.vs;
       const R ze = R(0.5) * (zr[v0] + zr[v1]);
-      const R* kr = kc + (size_t)j * g.cs;
-      const R kgrad = (kr[c1] - kr[c0]) * invd_r;
+      const R* kr = ke + (size_t)j * g.es;
+      const R kgrad = ((kr[rh[2]] + kr[rh[3]]) - (kr[rh[0]] + kr[rh[1]])) * third * invd_r;
       const double* wa = w + (size_t)j * g.cs;
       const double* wb = wa + g.cs;
       const R wef = (R)(0.5 * (0.5 * (wa[c0] + wa[c1]) + 0.5 * (wb[c0] + wb[c1])));
       // this edge's share of the horizontal advection of w at half level j:
       // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
       if (j > 0) gw[re] = le * ie_top * (R)(wa[c1] - wa[c0]);
-      const R vt = vts.apply(vn + (size_t)j * g.es, e);
+      const R vt = vtf[re];
       const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
       const size_t rc = (size_t)j * g.cs;
       const double exr = exref[j];
@@ -959,7 +968,8 @@ inline Geom geom_of(int phase, const DevGrid& g, const Tile* T) {
     case K_VC_P:
     case K_VC_C: {
       const Tile& t = T[T_VC];
-      return {cdiv(g.nc, t.threads) + cdiv(g.nv, t.threads), cdiv(g.K, t.kb), t.threads, 0};
+      const int nbx = cdiv(g.ne, t.threads) + cdiv(g.nv, t.threads) + (phase == K_VC_C ? cdiv(g.nc, t.threads) : 0);
+      return {nbx, cdiv(g.K, t.kb), t.threads, 0};
     }
     case K_EDGE_P:
     case K_EDGE_C: {
@@ -1005,12 +1015,12 @@ SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& 
   SubstepArgs<R> s;
   int lm;
   const int P = col_chunks_lm(g.K, &lm);
-  const int ncb = cdiv(g.nc, T[T_VC].threads);
-  s.vc_p = {b.vn, b.zeta, b.kc, nullptr, nullptr, ncb, T[T_VC].kb};
-  s.e_p = {b.vn, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
+  const int neb = cdiv(g.ne, T[T_VC].threads), nvb = cdiv(g.nv, T[T_VC].threads);
+  s.vc_p = {b.vn, b.zeta, b.vt, b.kc, nullptr, nullptr, neb, nvb, T[T_VC].kb};
+  s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
   s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr}, c, P};
-  s.vc_c = {b.vns, b.zeta, b.kc, b.d2, b.dvn, ncb, T[T_VC].kb};
-  s.e_c = {b.vns, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
+  s.vc_c = {b.vns, b.zeta, b.vt, b.kc, b.d2, b.dvn, neb, nvb, T[T_VC].kb};
+  s.e_c = {b.vns, b.zeta, b.kc, b.vt, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
   s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, P};
   return s;
 }

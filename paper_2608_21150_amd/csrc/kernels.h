@@ -83,7 +83,7 @@ struct Bufs {
   // state at the start of the substep
   const R* vn;
   const double *w, *rho, *ex, *th;
-  // workspace
+  // workspace (kc: K_e at edges [K][es] during the substeps)
   R *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv;
   double *ws, *wtmp;
   R* gw;        // [K+1][es] edge terms of the horizontal advection of w

@@ -137,7 +137,7 @@ inline void default_tiles(const HostGrid& h, Tile* t) {
     int kb = (int)((long long)levels * nbx / 2048);
     return std::max(1, std::min(kb, 16));
   };
-  t[T_VC] = {256, kb_for(h.nc + h.nv, h.K)};
+  t[T_VC] = {256, kb_for(h.ne + h.nv, h.K)};
   t[T_EDGE] = {256, kb_for(h.ne, h.K)};
   t[T_DVERT] = {256, kb_for(h.nv, h.K)};
   t[T_DCELL] = {256, kb_for(h.nc + h.nv, h.K + 1)};
