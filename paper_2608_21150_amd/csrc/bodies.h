@@ -213,23 +213,25 @@ struct BEdge {
     const double* idzf = vt_row(g, VT_IDZF);
     const double* exref = vt_row(g, VT_EXREF);
     const int k0 = by * kb, k1 = min(K, k0 + kb);
+    // values of the level above and of half level j carried from the
+    // previous level: vn(j-1), vn(j) and w at c0, c1 on half level j
+    R vup = vn[(size_t)max(k0 - 1, 0) * g.es + e];
+    R vj = vn[(size_t)k0 * g.es + e];
+    double wa0 = w[(size_t)k0 * g.cs + c0], wa1 = w[(size_t)k0 * g.cs + c1];
     for (int j = k0; j < k1; ++j) {
       const size_t re = (size_t)j * g.es + e;
-      const R vj = vn[re];
-      const R vup = j > 0 ? vn[re - g.es] : vj;
       const R vdn = j < K - 1 ? vn[re + g.es] : vj;
+      const double wb0 = w[(size_t)(j + 1) * g.cs + c0], wb1 = w[(size_t)(j + 1) * g.cs + c1];
       const R ie_top = j > 0 ? R(0.5) * (vup + vj) : vj;
       const R ie_bot = j < K - 1 ? R(0.5) * (vj + vdn) : vj;
       const R* zr = zeta + (size_t)j * g.vs;
       const R ze = R(0.5) * (zr[v0] + zr[v1]);
       const R* kr = ke + (size_t)j * g.es;
       const R kgrad = ((kr[rh[2]] + kr[rh[3]]) - (kr[rh[0]] + kr[rh[1]])) * third * invd_r;
-      const double* wa = w + (size_t)j * g.cs;
-      const double* wb = wa + g.cs;
-      const R wef = (R)(0.5 * (0.5 * (wa[c0] + wa[c1]) + 0.5 * (wb[c0] + wb[c1])));
+      const R wef = (R)(0.5 * (0.5 * (wa0 + wa1) + 0.5 * (wb0 + wb1)));
       // this edge's share of the horizontal advection of w at half level j:
       // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
-      if (j > 0) gw[re] = le * ie_top * (R)(wa[c1] - wa[c0]);
+      if (j > 0) gw[re] = le * ie_top * (R)(wa1 - wa0);
       const R vt = vtf[re];
       const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
       const size_t rc = (size_t)j * g.cs;
@@ -244,6 +246,10 @@ struct BEdge {
         const R dd = (d2[rc + c1] - d2[rc + c0]) * invd_r;
         vout[re] = vn_now[re] + (R)cf.dtau * ((R)cf.a0 * tvn0[re] + (R)cf.a1 * tvn - pgf) - (R)cf.c4a2 * dd;
       }
+      vup = vj;
+      vj = vdn;
+      wa0 = wb0;
+      wa1 = wb1;
     }
   }
 };
