@@ -250,14 +250,16 @@ dc_status dc_ensemble_destroy(dc_ensemble *ens);
  * Parameters (DC_MLP_NPARAMS floats, row-major): W1 [18][64], b1 [64],
  * W2 [64][64], b2 [64], w3 [64], b3 [1]; y = W3 gelu(W2 gelu(W1 x' + b1) + b2)
  * + b3 with x' = (x - mean) / std, and T = y * target_std.
- * Surrogate step: every judge_every-th step (the first included) runs the
- * plain diffusion, keeps its viscosity for w, and flags every edge column
- * whose residual dt |T_mlp - T_plain|_2 / max(|vn|_2, sqrt(K) m/s) exceeds
- * the threshold (flags hold until the next judge step).  The other steps
- * add dt T_mlp to vn except on flagged columns and on columns with a
- * feature outside the normalisation range, which run the plain vn
- * diffusion (and refresh their viscosity); w is diffused with the held
- * viscosity.  An MLP must outlive the states it is set on.
+ * Surrogate step: the plain diffusion's front runs every step (viscosity,
+ * L1, div L1 and curl L1, which the features use, and the w diffusion); the
+ * network then stands in for the vn update (the second Laplacian term and
+ * the update itself).  Every judge_every-th step (the first included) runs
+ * the plain vn update and flags every edge column whose residual
+ * dt |T_mlp - T_plain|_2 / max(|vn|_2, sqrt(K) m/s) exceeds the threshold
+ * (flags hold until the next judge step).  The other steps add dt T_mlp to
+ * vn except on flagged columns and on columns with a feature outside the
+ * normalisation range, which take the plain vn update.  An MLP must
+ * outlive the states it is set on.
  */
 #define DC_MLP_NFEATURES 18
 #define DC_MLP_NPARAMS 5441

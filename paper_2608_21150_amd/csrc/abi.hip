@@ -47,7 +47,7 @@ size_t elem_size(dc_precision prec) { return prec == DC_PREC_MIXED ? sizeof(floa
 
 struct Layout {
   size_t vt, tvn0, vns, kc, d2, zeta, vv, gw, dvn, wstar, wtmp, tw0, fe, tau, dpart, dout;
-  size_t s_tmlp, s_nu, s_fj, s_fr, s_cnt;  // surrogate mode only
+  size_t s_tmlp, s_cl, s_fj, s_fr, s_cnt;  // surrogate mode only
   size_t total;
 };
 
@@ -78,10 +78,10 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff)
   const int nblk = (h.nc + 255) / 256 + (h.ne + 255) / 256;
   L.dpart = take(5 * (size_t)nblk * 8);
   L.dout = take(8 * 8);
-  L.s_tmlp = L.s_nu = L.s_fj = L.s_fr = L.s_cnt = 0;
+  L.s_tmlp = L.s_cl = L.s_fj = L.s_fr = L.s_cnt = 0;
   if (diff == DC_DIFF_SURROGATE) {
     L.s_tmlp = take(K * h.es * r);
-    L.s_nu = take(K * h.es * r);
+    L.s_cl = take(K * h.vs * r);  // curl L1 of the diffusion front
     L.s_fj = take((size_t)h.es * 4);
     L.s_fr = take((size_t)h.es * 4);
     L.s_cnt = take(8 * 4);  // 4 int counters, then one 64-bit counter
@@ -379,7 +379,7 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->diag_out = reinterpret_cast<double*>(w + L.dout);
   if (diff == DC_DIFF_SURROGATE) {
     s->sur_tmlp = w + L.s_tmlp;
-    s->sur_nu = w + L.s_nu;
+    s->sur_cl = w + L.s_cl;
     s->sur_fj = reinterpret_cast<int*>(w + L.s_fj);
     s->sur_fr = reinterpret_cast<int*>(w + L.s_fr);
     s->sur_cnt = reinterpret_cast<int*>(w + L.s_cnt);

@@ -101,6 +101,17 @@ template <typename R>
 void launch_diffusion(const DevGrid& g, R* vn, const double* w_in, double* w_out, R* vt_l1, R* nu, R* kc_div,
                       R* d2_divl1, R* zeta, R* vv, const StepCoef& c, const Tile* tiles, hipStream_t s,
                       Prof* prof);
+// The diffusion in two parts: the front (vertex vectors and vorticity, div vn,
+// L1 and the viscosity, div L1 and curl L1, the w diffusion) and the back
+// (L2 and the vn update).  curll1 may differ from zeta so that the vorticity
+// survives the front.
+template <typename R>
+void launch_diffusion_front(const DevGrid& g, const R* vn, const double* w_in, double* w_out, R* l1, R* nu, R* dv,
+                            R* dl1, R* zeta, R* curll1, R* vv, const StepCoef& c, const Tile* tiles, hipStream_t s,
+                            Prof* prof);
+template <typename R>
+void launch_diffusion_back(const DevGrid& g, R* vn, const R* l1, const R* nu, const R* dl1, const R* curll1,
+                           const StepCoef& c, const Tile* tiles, hipStream_t s, Prof* prof);
 template <typename R>
 void launch_diag(const DevGrid& g, const R* vn, const double* w, const double* rho, const double* th,
                  const double* ex, double* partial, double* out, hipStream_t s);

@@ -184,6 +184,27 @@ void launch_diffusion(const DevGrid& g, R* vn, const double* w_in, double* w_out
 }
 
 template <typename R>
+void launch_diffusion_front(const DevGrid& g, const R* vn, const double* w_in, double* w_out, R* l1, R* nu, R* dv,
+                            R* dl1, R* zeta, R* curll1, R* vv, const StepCoef& c, const Tile* T, hipStream_t s,
+                            Prof* prof) {
+  using namespace bodies;
+  DiffusionArgs<R> d = diffusion_args<R>(g, const_cast<R*>(vn), w_in, w_out, l1, nu, dv, dl1, zeta, vv, c, T);
+  d.cv.curll1 = curll1;
+  one<BDvert<R>>(K_DVERT, g, d.dv, T, s, prof);
+  one<BDiv<R>>(K_DDIV, g, d.dd, T, s, prof);
+  one<BDedge1<R>>(K_DEDGE1, g, d.d1, T, s, prof);
+  one<BDcv2<R>>(K_DCV2, g, d.cv, T, s, prof);
+}
+
+template <typename R>
+void launch_diffusion_back(const DevGrid& g, R* vn, const R* l1, const R* nu, const R* dl1, const R* curll1,
+                           const StepCoef& c, const Tile* T, hipStream_t s, Prof* prof) {
+  using namespace bodies;
+  const typename BDedge2<R>::Args a{vn, l1, nu, dl1, curll1, c, T[T_DEDGE].kb};
+  one<BDedge2<R>>(K_DEDGE2, g, a, T, s, prof);
+}
+
+template <typename R>
 void launch_diag(const DevGrid& g, const R* vn, const double* w, const double* rho, const double* th,
                  const double* ex, double* partial, double* out, hipStream_t s) {
   const int ncb = (g.nc + kDiagThreads - 1) / kDiagThreads;
@@ -200,6 +221,16 @@ template void launch_diffusion<double>(const DevGrid&, double*, const double*, d
                                        double*, double*, double*, const StepCoef&, const Tile*, hipStream_t, Prof*);
 template void launch_diffusion<float>(const DevGrid&, float*, const double*, double*, float*, float*, float*, float*,
                                       float*, float*, const StepCoef&, const Tile*, hipStream_t, Prof*);
+template void launch_diffusion_front<double>(const DevGrid&, const double*, const double*, double*, double*,
+                                             double*, double*, double*, double*, double*, double*, const StepCoef&,
+                                             const Tile*, hipStream_t, Prof*);
+template void launch_diffusion_front<float>(const DevGrid&, const float*, const double*, double*, float*, float*,
+                                            float*, float*, float*, float*, float*, const StepCoef&, const Tile*,
+                                            hipStream_t, Prof*);
+template void launch_diffusion_back<double>(const DevGrid&, double*, const double*, const double*, const double*,
+                                            const double*, const StepCoef&, const Tile*, hipStream_t, Prof*);
+template void launch_diffusion_back<float>(const DevGrid&, float*, const float*, const float*, const float*,
+                                           const float*, const StepCoef&, const Tile*, hipStream_t, Prof*);
 template void launch_diag<double>(const DevGrid&, const double*, const double*, const double*, const double*,
                                   const double*, double*, double*, hipStream_t);
 template void launch_diag<float>(const DevGrid&, const float*, const double*, const double*, const double*,

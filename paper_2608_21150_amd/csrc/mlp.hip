@@ -145,53 +145,41 @@ __device__ void forward64(const SW& s, const bf16* xs, bf16* hs, float y[4][4]) 
   }
 }
 
-// div L1 at cell c and curl L1 at vertex v, with L1 at the edges evaluated
-// from the divergence (dr) and vorticity (zr) rows of one level: the plain
-// diffusion's expressions (its div and curl of the stored L1 row)
-template <typename R>
-__device__ __forceinline__ R divl1_at(const DevGrid& g, const R* dr, const R* zr, int c) {
-  const int i0 = g.c2e[c], i1 = g.c2e[g.cs + c], i2 = g.c2e[2 * g.cs + c];
-  const R k0 = (R)g.kdiv[c], k1 = (R)g.kdiv[g.cs + c], k2 = (R)g.kdiv[2 * g.cs + c];
-  return k0 * dif_l1<R>(g, dr, zr, i0) + k1 * dif_l1<R>(g, dr, zr, i1) + k2 * dif_l1<R>(g, dr, zr, i2);
-}
-template <typename R>
-__device__ __forceinline__ R curll1_at(const DevGrid& g, const R* dr, const R* zr, int v) {
-  R z = (R)g.kcurl[v] * dif_l1<R>(g, dr, zr, g.v2e[v]);
-  for (int s = 1; s < 6; ++s) z += (R)g.kcurl[s * g.vs + v] * dif_l1<R>(g, dr, zr, g.v2e[s * g.vs + v]);
-  return z;
-}
-
 // The 18 raw features of edge e at level k, from vn, vt (edges), D = div vn
-// (cells), Z = curl vn and the vertex vectors V (vertices, three component
-// planes `plane` apart).  Stencil values enter as centred pairs, the mean of
-// the two points and their difference over their distance, formed in the
-// path's precision before the network's BF16 rounding: vn_e, vt_e; D at
-// c0, c1; Z at the end vertices v0, v1; div L1 at c0, c1; curl L1 at v0, v1;
-// the four rhombus derivatives; Z at the two opposite rhombus vertices;
-// l_e / mean l, d_e / mean d.
+// (cells), Z = curl vn (vertices), DL = div L1 (cells), CL = curl L1
+// (vertices) and the vertex vectors V (three component planes `plane`
+// apart); the fields are those of the plain diffusion.  Stencil values
+// enter as centred pairs, the mean of the two points and their difference
+// over their distance, formed in the path's precision before the network's
+// BF16 rounding: vn_e, vt_e; D at c0, c1; Z at the end vertices v0, v1;
+// div L1 at c0, c1; curl L1 at v0, v1; the four rhombus derivatives; Z at the
+// two opposite rhombus vertices; l_e / mean l, d_e / mean d.
+struct FeatIn {
+  const void *vn, *vt, *D, *Z, *DL, *CL, *V;
+};
 template <typename R>
-__device__ __forceinline__ void features(const DevGrid& g, const R* vn, const R* vt, const R* D, const R* Z,
-                                         const R* V, size_t plane, int e, int k, double lbar, double dbar,
+__device__ __forceinline__ void features(const DevGrid& g, const FeatIn& in, int e, int k, double lbar, double dbar,
                                          float f[NIN]) {
-  const R* dr = D + (size_t)k * g.cs;
-  const R* zr = Z + (size_t)k * g.vs;
-  const R* vx = V + (size_t)k * g.vs;
+  const size_t plane = (size_t)g.K * g.vs;
+  const R* dr = static_cast<const R*>(in.D) + (size_t)k * g.cs;
+  const R* zr = static_cast<const R*>(in.Z) + (size_t)k * g.vs;
+  const R* dlr = static_cast<const R*>(in.DL) + (size_t)k * g.cs;
+  const R* clr = static_cast<const R*>(in.CL) + (size_t)k * g.vs;
+  const R* vx = static_cast<const R*>(in.V) + (size_t)k * g.vs;
   const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
   const int v0 = g.e2c2v[e], v1 = g.e2c2v[g.es + e], v2 = g.e2c2v[2 * g.es + e], v3 = g.e2c2v[3 * g.es + e];
   const R invd = (R)g.invd[e], invl = (R)g.invl[e], invlr = (R)g.invlr[e];
   const R half = R(0.5);
-  f[0] = (float)vn[(size_t)k * g.es + e];
-  f[1] = (float)vt[(size_t)k * g.es + e];
+  f[0] = (float)static_cast<const R*>(in.vn)[(size_t)k * g.es + e];
+  f[1] = (float)static_cast<const R*>(in.vt)[(size_t)k * g.es + e];
   f[2] = (float)(half * (dr[c0] + dr[c1]));
   f[3] = (float)((dr[c1] - dr[c0]) * invd);
   f[4] = (float)(half * (zr[v0] + zr[v1]));
   f[5] = (float)((zr[v1] - zr[v0]) * invl);
-  const R a0 = divl1_at<R>(g, dr, zr, c0), a1 = divl1_at<R>(g, dr, zr, c1);
-  f[6] = (float)(half * (a0 + a1));
-  f[7] = (float)((a1 - a0) * invd);
-  const R b0 = curll1_at<R>(g, dr, zr, v0), b1 = curll1_at<R>(g, dr, zr, v1);
-  f[8] = (float)(half * (b0 + b1));
-  f[9] = (float)((b1 - b0) * invl);
+  f[6] = (float)(half * (dlr[c0] + dlr[c1]));
+  f[7] = (float)((dlr[c1] - dlr[c0]) * invd);
+  f[8] = (float)(half * (clr[v0] + clr[v1]));
+  f[9] = (float)((clr[v1] - clr[v0]) * invl);
   R d[4];
   dif_rhombus<R>(g, vx, vx + plane, vx + 2 * plane, e, d);
 #pragma unroll
@@ -222,9 +210,7 @@ __global__ void __launch_bounds__(256) k_vt(DevGrid g, const R* __restrict__ vn,
 // gets flag_range[e] = 1 (plain stores of one value: order independent).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(128) k_infer(DevGrid g, const R* __restrict__ vn, const R* __restrict__ vt,
-                                               const R* __restrict__ D, const R* __restrict__ Z,
-                                               const R* __restrict__ V, const float* __restrict__ par, const Norm* __restrict__ nrm,
+__global__ void __launch_bounds__(128) k_infer(DevGrid g, FeatIn fin, const float* __restrict__ par, const Norm* __restrict__ nrm,
                                                double lbar, double dbar, R* __restrict__ tout,
                                                int* __restrict__ flag_range) {
   __shared__ SW s;
@@ -242,7 +228,7 @@ __global__ void __launch_bounds__(128) k_infer(DevGrid g, const R* __restrict__ 
     const int e = e0 + l;
     float f[NIN];
     if (e < g.ne) {
-      features<R>(g, vn, vt, D, Z, V, (size_t)g.K * g.vs, e, k, lbar, dbar, f);
+      features<R>(g, fin, e, k, lbar, dbar, f);
       bool out = false;
 #pragma unroll
       for (int i = 0; i < NIN; ++i) out |= !(f[i] >= nrm->fmin[i] && f[i] <= nrm->fmax[i]);
@@ -268,28 +254,6 @@ __global__ void __launch_bounds__(128) k_infer(DevGrid g, const R* __restrict__ 
   }
 }
 
-// Plain vn diffusion of one (edge, level) from the pre-diffusion fields
-// D = div vn (cells), Z = curl vn (vertices) and the vertex vectors V,
-// with the same expressions as the plain kernels; also returns nu.
-template <typename R>
-__device__ R plain_vn(const DevGrid& g, R vn, const R* D, const R* Z, const R* V, size_t plane, int e, int k,
-                      const StepCoef& cf, R* nu_out) {
-  const R* dr = D + (size_t)k * g.cs;
-  const R* zr = Z + (size_t)k * g.vs;
-  const R* vx = V + (size_t)k * g.vs;
-  const R l1e = dif_l1<R>(g, dr, zr, e);
-  const R nu = dif_nu<R>(g, vx, vx + plane, vx + 2 * plane, e, cf);
-  R dl[2], cl[2];
-  for (int side = 0; side < 2; ++side) {
-    dl[side] = divl1_at<R>(g, dr, zr, g.e2c[side * g.es + e]);
-    cl[side] = curll1_at<R>(g, dr, zr, g.e2v[side * g.es + e]);
-  }
-  const R l2 = dif_l2<R>(g, dl[0], dl[1], cl[0], cl[1], e);
-  const double ae = g.ae[e];
-  *nu_out = nu;
-  return dif_update<R>(vn, (R)cf.dt, nu, l1e, (R)(cf.k4 * ae * ae), l2);
-}
-
 // Adds the wave's count of lanes with pred set to *c (one atomic per wave;
 // integer sums are order independent).  Every lane of the wave must call it.
 __device__ __forceinline__ void wave_count(bool pred, int* c) {
@@ -301,14 +265,15 @@ __device__ __forceinline__ void wave_count64(bool pred, unsigned long long* c) {
   if ((threadIdx.x & 63) == 0 && b) atomicAdd(c, (unsigned long long)__popcll(b));
 }
 
-// apply: vn += dt T_mlp, or the plain update on flagged columns (which also
-// refresh their held viscosity).  cnt[1] counts range flags, cnt[2] fallback
-// columns of this step; the 64-bit counter at cnt + 4 sums the fallback
-// columns since the network was set.
+// apply: vn += dt T_mlp, or on flagged columns the plain update from the
+// fields of the plain diffusion's front (the expressions of its last
+// kernel).  cnt[1] counts range flags, cnt[2] fallback columns of this step;
+// the 64-bit counter at cnt + 4 sums the fallback columns since the network
+// was set.
 template <typename R>
 __global__ void __launch_bounds__(256) k_apply(DevGrid g, R* __restrict__ vn, const R* __restrict__ tmlp,
-                                               const R* __restrict__ D, const R* __restrict__ Z,
-                                               const R* __restrict__ V, R* __restrict__ nu_held,
+                                               const R* __restrict__ l1, const R* __restrict__ nu,
+                                               const R* __restrict__ dl1, const R* __restrict__ cl1,
                                                const int* __restrict__ fj, const int* __restrict__ fr,
                                                int* __restrict__ cnt, StepCoef cf) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,16 +284,20 @@ __global__ void __launch_bounds__(256) k_apply(DevGrid g, R* __restrict__ vn, co
   wave_count(fb, &cnt[2]);
   wave_count64(fb, reinterpret_cast<unsigned long long*>(cnt + 4));
   if (!in) return;
-  const size_t plane = (size_t)g.K * g.vs;
+  const R dt = (R)cf.dt;
   if (fb) {
+    const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
+    const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
+    const double ae = g.ae[e];
+    const R k4a2 = (R)(cf.k4 * ae * ae);
     for (int k = 0; k < g.K; ++k) {
+      const R* dr = dl1 + (size_t)k * g.cs;
+      const R* zr = cl1 + (size_t)k * g.vs;
+      const R l2 = dif_l2<R>(g, dr[c0], dr[c1], zr[v0], zr[v1], e);
       const size_t r = (size_t)k * g.es + e;
-      R nu;
-      vn[r] = plain_vn<R>(g, vn[r], D, Z, V, plane, e, k, cf, &nu);
-      nu_held[r] = nu;
+      vn[r] = dif_update<R>(vn[r], dt, nu[r], l1[r], k4a2, l2);
     }
   } else {
-    const R dt = (R)cf.dt;
     for (int k = 0; k < g.K; ++k) {
       const size_t r = (size_t)k * g.es + e;
       vn[r] = vn[r] + dt * tmlp[r];
@@ -368,16 +337,6 @@ __global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = a[i];
 }
 
-// w diffusion with the held viscosity field
-template <typename R>
-__global__ void __launch_bounds__(256) k_wdiff(DevGrid g, const double* __restrict__ w_in, double* __restrict__ w_out,
-                                               const R* __restrict__ nu, StepCoef cf) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (c >= g.nc) return;
-  w_out[(size_t)k * g.cs + c] = dif_w<R>(g, w_in, nu, c, k, cf);
-}
-
 // ---------------------------------------------------------------------------
 // sampler: a counter-based Feistel permutation of [0, n) (sampling without
 // replacement): four rounds of a 32-bit integer mixer on the two halves of
@@ -414,9 +373,7 @@ __host__ __device__ __forceinline__ unsigned long long feistel(unsigned long lon
 // features of the sampled points (pre-diffusion fields); idx_out keeps the
 // flat internal index k * ne + e of every sample
 template <typename R>
-__global__ void __launch_bounds__(256) k_sample_feat(DevGrid g, const R* __restrict__ vn, const R* __restrict__ vt,
-                                                     const R* __restrict__ D, const R* __restrict__ Z,
-                                                     const R* __restrict__ V, double lbar,
+__global__ void __launch_bounds__(256) k_sample_feat(DevGrid g, FeatIn fin, double lbar,
                                                      double dbar, unsigned long long key, long long nsamp,
                                                      float* __restrict__ buf, long long stride, long long offset,
                                                      long long* __restrict__ idx_out) {
@@ -426,7 +383,7 @@ __global__ void __launch_bounds__(256) k_sample_feat(DevGrid g, const R* __restr
   const unsigned long long idx = feistel((unsigned long long)i, N, key);
   const int k = (int)(idx / g.ne), e = (int)(idx % g.ne);
   float f[NIN];
-  features<R>(g, vn, vt, D, Z, V, (size_t)g.K * g.vs, e, k, lbar, dbar, f);
+  features<R>(g, fin, e, k, lbar, dbar, f);
   for (int x = 0; x < NIN; ++x) buf[x * stride + offset + i] = f[x];
   if (idx_out) idx_out[i] = (long long)idx;
 }
@@ -764,18 +721,21 @@ void mean_lengths(const HostGrid& h, double* lbar, double* dbar) {
   *dbar = sd / h.ne;
 }
 
-// vorticity, vertex vectors and divergence with the plain path's kernels,
-// then vt (into the substep workspace field vns, idle during diffusion)
+// The plain diffusion's front on the current vn (w diffused into the state's
+// w with the fresh viscosity; curl L1 into its own buffer so that the
+// vorticity survives), then vt for the features into the substep workspace
+// field vns (idle during the diffusion).
 template <typename R>
-void prep_fields(dc_state* s, const R* vn, hipStream_t st) {
+FeatIn front_and_features(dc_state* s, const StepCoef& c, hipStream_t st) {
   const DevGrid& g = s->d;
-  const typename BDvert<R>::Args dv{vn, static_cast<R*>(s->vv), static_cast<R*>(s->zeta), s->tiles[T_DVERT].kb};
-  const Geom gv = geom_of(K_DVERT, g, s->tiles);
-  k_one<BDvert<R>><<<dim3(gv.nbx, gv.nby), gv.threads, 0, st>>>(g, dv);
-  const typename BDiv<R>::Args dd{vn, static_cast<R*>(s->kc), s->tiles[T_DCELL].kb};
-  const Geom gd = geom_of(K_DDIV, g, s->tiles);
-  k_one<BDiv<R>><<<dim3(gd.nbx, gd.nby), gd.threads, 0, st>>>(g, dd);
+  const dc_fields& cur = s->buf[s->cur];
+  R* vn = static_cast<R*>(cur.vn);
+  launch_diffusion_front<R>(g, vn, s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt),
+                            static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
+                            static_cast<R*>(s->zeta), static_cast<R*>(s->sur_cl), static_cast<R*>(s->vv), c, s->tiles,
+                            st, nullptr);
   k_vt<R><<<dim3((g.ne + 255) / 256, g.K), 256, 0, st>>>(g, vn, static_cast<R*>(s->vns));
+  return FeatIn{vn, s->vns, s->kc, s->zeta, s->d2, s->sur_cl, s->vv};
 }
 
 }  // namespace
@@ -783,43 +743,40 @@ void prep_fields(dc_state* s, const R* vn, hipStream_t st) {
 namespace dc {
 
 // One diffusion step of a surrogate-mode state on its current buffer set.
-// Every judge_every-th step (the first included) runs the plain diffusion,
-// keeps its viscosity and flags the columns whose surrogate residual
-// exceeds the threshold; the other steps apply the surrogate except on
-// flagged columns and on columns with out-of-range features.
+// The plain diffusion's front runs every step (ν, L1, div and curl of L1 and
+// the w diffusion); every judge_every-th step (the first included) then
+// runs its last kernel and flags the columns whose surrogate residual
+// exceeds the threshold; the other steps apply the surrogate tendency except
+// on flagged columns and on columns with out-of-range features, which take
+// the plain update.
 template <typename R>
 void surrogate_diffusion(dc_state* s, const StepCoef& c) {
   SurCtx& sc = *s->sur;
   hipStream_t st = s->stream;
   const DevGrid& g = s->d;
-  const dc_fields& cur = s->buf[s->cur];
-  R* vn = static_cast<R*>(cur.vn);
+  R* vn = static_cast<R*>(s->buf[s->cur].vn);
   R* tm = static_cast<R*>(s->sur_tmlp);
-  R* nu = static_cast<R*>(s->sur_nu);
   const bool judge = sc.steps % sc.judge_every == 0;
   ++sc.steps;
-  prep_fields<R>(s, vn, st);
+  const FeatIn fin = front_and_features<R>(s, c, st);
   k_fill_int<<<(g.ne + 255) / 256, 256, 0, st>>>(s->sur_fr, g.ne, 0);
   const int total = ((g.ne + 127) / 128) * g.K;
-  k_infer<R><<<std::min(total, 4096), 128, 0, st>>>(g, vn, static_cast<const R*>(s->vns), static_cast<const R*>(s->kc),
-                                                    static_cast<const R*>(s->zeta), static_cast<const R*>(s->vv),
-                                                    sc.mlp->par, sc.mlp->nrm,
-                                                    s->sur_lbar, s->sur_dbar, tm, s->sur_fr);
+  k_infer<R><<<std::min(total, 4096), 128, 0, st>>>(g, fin, sc.mlp->par, sc.mlp->nrm, s->sur_lbar, s->sur_dbar, tm,
+                                                    s->sur_fr);
+  const R* l1 = static_cast<const R*>(s->vt);
+  const R* nu = static_cast<const R*>(s->tvn0);
+  const R* dl1 = static_cast<const R*>(s->d2);
+  const R* cl1 = static_cast<const R*>(s->sur_cl);
   if (judge) {
     ++sc.judge_steps;
     R* old = static_cast<R*>(s->vns);  // vt is no longer needed
     k_copy<R><<<1024, 256, 0, st>>>(vn, old, (size_t)g.K * g.es);
-    launch_diffusion<R>(g, vn, s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt), nu,
-                        static_cast<R*>(s->kc), static_cast<R*>(s->d2), static_cast<R*>(s->zeta),
-                        static_cast<R*>(s->vv), c, s->tiles, st, nullptr);
+    launch_diffusion_back<R>(g, vn, l1, nu, dl1, cl1, c, s->tiles, st, nullptr);
     k_fill_int<<<1, 64, 0, st>>>(s->sur_cnt, 1, 0);
     k_judge<R><<<(g.ne + 255) / 256, 256, 0, st>>>(g, vn, old, tm, c.dt, sc.thr, s->sur_fj, s->sur_cnt);
   } else {
     k_fill_int<<<1, 64, 0, st>>>(s->sur_cnt + 1, 2, 0);
-    k_apply<R><<<(g.ne + 255) / 256, 256, 0, st>>>(g, vn, tm, static_cast<const R*>(s->kc),
-                                                   static_cast<const R*>(s->zeta), static_cast<const R*>(s->vv), nu,
-                                                   s->sur_fj, s->sur_fr, s->sur_cnt, c);
-    k_wdiff<R><<<dim3((g.nc + 255) / 256, g.K + 1), 256, 0, st>>>(g, s->wtmp, static_cast<double*>(cur.w), nu, c);
+    k_apply<R><<<(g.ne + 255) / 256, 256, 0, st>>>(g, vn, tm, l1, nu, dl1, cl1, s->sur_fj, s->sur_fr, s->sur_cnt, c);
   }
 }
 
@@ -847,18 +804,14 @@ dc_status collect_impl(dc_state* s, double dt, int nsub, unsigned long long key,
     const dc_fields& f = s->buf[s->cur];
     k_copy<double><<<1024, 256, 0, st>>>(static_cast<const double*>(f.w), s->wtmp, (size_t)(g.K + 1) * g.cs);
   }
-  const dc_fields& cur = s->buf[s->cur];
-  R* vn = static_cast<R*>(cur.vn);
+  R* vn = static_cast<R*>(s->buf[s->cur].vn);
   R* old = static_cast<R*>(s->sur_tmlp);
-  prep_fields<R>(s, vn, st);
-  k_sample_feat<R><<<(unsigned)((nsamp + 255) / 256), 256, 0, st>>>(
-      g, vn, static_cast<const R*>(s->vns), static_cast<const R*>(s->kc), static_cast<const R*>(s->zeta),
-      static_cast<const R*>(s->vv), s->sur_lbar,
-      s->sur_dbar, key, nsamp, buf, stride, offset, idx_dev);
+  const FeatIn fin = front_and_features<R>(s, c, st);
+  k_sample_feat<R><<<(unsigned)((nsamp + 255) / 256), 256, 0, st>>>(g, fin, s->sur_lbar, s->sur_dbar, key, nsamp, buf,
+                                                                    stride, offset, idx_dev);
   k_copy<R><<<1024, 256, 0, st>>>(vn, old, (size_t)g.K * g.es);
-  launch_diffusion<R>(g, vn, s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt), static_cast<R*>(s->tvn0),
-                      static_cast<R*>(s->kc), static_cast<R*>(s->d2), static_cast<R*>(s->zeta),
-                      static_cast<R*>(s->vv), c, s->tiles, st, nullptr);
+  launch_diffusion_back<R>(g, vn, static_cast<const R*>(s->vt), static_cast<const R*>(s->tvn0),
+                           static_cast<const R*>(s->d2), static_cast<const R*>(s->sur_cl), c, s->tiles, st, nullptr);
   k_sample_target<R><<<(unsigned)((nsamp + 255) / 256), 256, 0, st>>>(g, old, vn, dt, key, nsamp, buf, stride, offset);
   ML_TRY(hipGetLastError());
   return DC_OK;

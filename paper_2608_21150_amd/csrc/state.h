@@ -48,11 +48,11 @@ struct dc_state {
   void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv, *gw, *dvn;
   double *wstar, *wtmp, *tw0, *fe, *tau, *diag_part, *diag_out;
   // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
-  // held viscosity [K][es], judge and range flags [es], counters (4 int,
-  // then one 64-bit)
+  // curl L1 of the diffusion front [K][vs], judge and range flags [es],
+  // counters (4 int, then one 64-bit)
   dc::SurCtx* sur = nullptr;
   void* sur_tmlp = nullptr;
-  void* sur_nu = nullptr;
+  void* sur_cl = nullptr;
   int* sur_fj = nullptr;
   int* sur_fr = nullptr;
   int* sur_cnt = nullptr;
