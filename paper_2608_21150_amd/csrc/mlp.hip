@@ -50,15 +50,36 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16;
 
-__device__ __forceinline__ bf16 to_bf16(float x) {
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16)(u >> 16);
+// FP32 -> BF16, round to nearest even (gfx950 converts natively)
+__device__ __forceinline__ bf16 to_bf16(float x) { return __builtin_bit_cast(bf16, (__bf16)x); }
+
+// erf for x >= 0 by Abramowitz & Stegun 7.1.26 (absolute error <= 1.5e-7,
+// far below the BF16 resolution of the network's activations), branch-free;
+// e = exp(-x^2) is passed in so that GELU and its derivative share it.
+__device__ __forceinline__ float erf_pos(float ax, float e) {
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  return 1.0f - poly * e;
 }
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_d(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+// Phi(x) = (1 + erf(x / sqrt 2)) / 2 and phi(x) = exp(-x^2 / 2) / sqrt(2 pi)
+__device__ __forceinline__ void normal_cdf_pdf(float x, float& cdf, float& pdf) {
+  const float u = x * 0.70710678118654752f;
+  const float e = __expf(-u * u);
+  const float er = erf_pos(fabsf(u), e);
+  cdf = 0.5f * (1.0f + copysignf(er, u));
+  pdf = e * 0.39894228040143268f;
+}
+// exact-erf GELU x Phi(x) and its derivative Phi(x) + x phi(x)
+__device__ __forceinline__ float gelu(float x) {
+  float c, d;
+  normal_cdf_pdf(x, c, d);
+  return x * c;
+}
+__device__ __forceinline__ void gelu_and_grad(float x, float& g, float& gd) {
+  float c, d;
+  normal_cdf_pdf(x, c, d);
+  g = x * c;
+  gd = c + x * d;
 }
 __device__ __forceinline__ s4 frag(const bf16* m, int ld, int r0, int k0) {
   const int l = threadIdx.x & 63;
@@ -498,9 +519,10 @@ __global__ void __launch_bounds__(128) k_train(const float* __restrict__ par, co
       f4 h;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float z = acc[t] + s.b1[16 * nt + j];
-        gd1[nt][t] = gelu_d(z);
-        h[t] = gelu(z);
+        float hv, gv;
+        gelu_and_grad(acc[t] + s.b1[16 * nt + j], hv, gv);
+        h[t] = hv;
+        gd1[nt][t] = gv;
       }
       h1f[nt] = pack(h);
 #pragma unroll
@@ -508,7 +530,7 @@ __global__ void __launch_bounds__(128) k_train(const float* __restrict__ par, co
     }
     __syncthreads();
     // layers 2 and 3, residual, dz2; dW2 += h1^T dz2
-    f4 z2[4];
+    f4 h2v[4], g2v[4];
     float yp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -517,8 +539,11 @@ __global__ void __launch_bounds__(128) k_train(const float* __restrict__ par, co
       for (int ks = 0; ks < 4; ++ks) acc = mfma(frag(hs, HS, 0, 16 * ks), frag(s.w2t, HS, 16 * nt, 16 * ks), acc);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        z2[nt][t] = acc[t] + s.b2[16 * nt + j];
-        yp[t] += gelu(z2[nt][t]) * s.w3[16 * nt + j];
+        float hv, gv;
+        gelu_and_grad(acc[t] + s.b2[16 * nt + j], hv, gv);
+        h2v[nt][t] = hv;
+        g2v[nt][t] = gv;
+        yp[t] += hv * s.w3[16 * nt + j];
       }
     }
     float dy[4];
@@ -537,8 +562,8 @@ __global__ void __launch_bounds__(128) k_train(const float* __restrict__ par, co
       f4 dz;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        dw3[nt] += gelu(z2[nt][t]) * dy[t];
-        dz[t] = dy[t] * s.w3[16 * nt + j] * gelu_d(z2[nt][t]);
+        dw3[nt] += h2v[nt][t] * dy[t];
+        dz[t] = dy[t] * s.w3[16 * nt + j] * g2v[nt][t];
         db2[nt] += dz[t];
       }
       dzf[nt] = pack(dz);
