@@ -340,7 +340,10 @@ struct BCol {
     const int P = args.P;
     extern __shared__ double s_red[];  // [6][P][64]
     const int K = g.K, cs = g.cs;
-    const int cl = threadIdx.x & 63, p = threadIdx.x >> 6;
+    // the wave index is uniform across the wave: let the compiler keep it,
+    // the chunk bounds and every row address derived from them in scalar
+    // registers
+    const int cl = threadIdx.x & 63, p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c0 = bx * 64 + cl;
     const bool ok = c0 < g.nc;
     const int c = ok ? c0 : 0;  // padding lanes compute column 0 and store nothing
