@@ -338,7 +338,10 @@ struct BCol {
     const ColArgs<R> a = args.a;
     const StepCoef cf = args.cf;
     const int P = args.P;
-    extern __shared__ double s_red[];  // [6][P][64]
+    // LDS: [6][P][64] interface system; s_stg: each wave's row of rho and
+    // theta_v at its current level (neighbour gathers inside the tile)
+    extern __shared__ double s_red[];
+    __shared__ double s_stg[8][2][64];
     const int K = g.K, cs = g.cs;
     // the wave index is uniform across the wave: let the compiler keep it,
     // the chunk bounds and every row address derived from them in scalar
@@ -368,6 +371,7 @@ struct BCol {
     // ---- forward sweep over levels h..h+n: explicit parts, rows, down sweep ----
     double cpv[LM], dpv[LM], lpv[LM];
     double drxv[LM + 1], dxxv[LM + 1];
+
     ColLev cur;
     col_load(g, a.rho, a.th, a.ex, h, c, cur);
     cur.w = a.w[(size_t)h * cs + c];
@@ -402,23 +406,38 @@ struct BCol {
           nx.w = a.w[(size_t)K * cs + c];
           nx.ws = 0.0;
         }
-        // mass and theta fluxes, explicit parts at full level j
+        // mass and theta fluxes, explicit parts at full level j; neighbour
+        // rho, theta_v inside the 64-column tile come from the other lanes'
+        // rows through LDS, the others from memory
         double dm = 0.0, dth = 0.0;
         {
           const R* vr = a.vnf + (size_t)j * g.es;
           const double* rr = a.rho + (size_t)j * cs;
           const double* tr = a.th + (size_t)j * cs;
+          s_stg[p][0][cl] = cur.rho;
+          s_stg[p][1][cl] = cur.th;
+          __builtin_amdgcn_wave_barrier();
           R vq[3];
   #pragma unroll
           for (int q = 0; q < 3; ++q) {
             vq[q] = vr[ie[q]];
-            const R rho_e = (R)(0.5 * (cur.rho + rr[nb[q]]));
-            const R th_e = (R)(0.5 * (cur.th + tr[nb[q]]));
+            // the LDS read is unconditional (masked index), the memory read
+            // only for neighbours outside the tile (written as selects: an
+            // if-statement form makes the gfx950 backend fail machine
+            // verification on the corrector)
+            const int lq = nb[q] - bx * 64;
+            double rn = s_stg[p][0][lq & 63];
+            double tn = s_stg[p][1][lq & 63];
+            rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
+            tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
+            const R rho_e = (R)(0.5 * (cur.rho + rn));
+            const R th_e = (R)(0.5 * (cur.th + tn));
             const R fm = rho_e * vq[q];
             const R ft = fm * th_e;
             dm += kd[q] * (double)fm;
             dth += kd[q] * (double)ft;
           }
+          __builtin_amdgcn_wave_barrier();
           // predictor: divergence of vn* for the corrector's damping (each
           // full level is stored by the chunk that owns it)
           if (!CORR && ok && (i >= 1 || p == 0))
