@@ -99,6 +99,11 @@ def test_ensemble_errors():
     with pytest.raises(D.DycoreError) as ei:
         D.Ensemble([items[0][1], items[0][1]])
     assert ei.value.code == D.DC_EINVAL
+    sur = D.State(items[0][0], diffusion="surrogate")  # surrogate states are stepped alone
+    with pytest.raises(D.DycoreError) as ei:
+        D.Ensemble([items[0][1], sur])
+    assert ei.value.code == D.DC_EINVAL
+    sur.close()
     E = D.Ensemble([st for _, st, _ in items])
     items[1][1].step(DT, NSUB)  # stepped alone: buffer sets now differ
     with pytest.raises(D.DycoreError) as ei:
