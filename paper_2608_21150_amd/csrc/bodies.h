@@ -690,21 +690,17 @@ __device__ __forceinline__ R dif_update(R vn, R dt, R nu, R l1, R k4a2, R l2) {
   return vn + dt * nu * l1 - k4a2 * l2;
 }
 // w at cell c, half level k after Smagorinsky diffusion with the edge
-// viscosity nu (averaged to the cell and the half level)
+// viscosity (na, nb: nu on the cell's three edges at the full levels k-1 and
+// k, averaged to the cell and the half level)
 template <typename R>
-__device__ __forceinline__ double dif_w(const DevGrid& g, const double* w_in, const R* nu, int c, int k,
+__device__ __forceinline__ double dif_w(const DevGrid& g, const double* w_in, const R* na, const R* nb, int c, int k,
                                         const StepCoef& cf) {
   const size_t r = (size_t)k * g.cs + c;
   double wn = w_in[r];
   if (cf.diffuse_w && k >= 1 && k <= g.K - 1) {
-    const R* na = nu + (size_t)(k - 1) * g.es;
-    const R* nbr = nu + (size_t)k * g.es;
     R nuc = R(0);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int ie = g.c2e[i * g.cs + c];
-      nuc += R(0.5) * (na[ie] + nbr[ie]);
-    }
+    for (int i = 0; i < 3; ++i) nuc += R(0.5) * (na[i] + nb[i]);
     nuc = nuc / R(3);
     const double* wr = w_in + (size_t)k * g.cs;
     double lw = 0.0;
@@ -860,24 +856,29 @@ struct BDcv2 {
     if (bx < ncb) {
       const int c = bx * blockDim.x + threadIdx.x;
       if (c >= g.nc) return;
-      int ie[3], nb[3];
-      R kd[3];
-      double kl[3];
+      int ie[3];
   #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        ie[i] = g.c2e[i * g.cs + c];
-        nb[i] = g.c2e2c[i * g.cs + c];
-        kd[i] = (R)g.kdiv[i * g.cs + c];
-        kl[i] = g.klap[i * g.cs + c];
-      }
+      for (int i = 0; i < 3; ++i) ie[i] = g.c2e[i * g.cs + c];
       const int k0 = by * kb, k1 = min(K + 1, k0 + kb);
+      // nu on the cell's edges at full level k - 1, carried from one half
+      // level to the next
+      R nup[3] = {R(0), R(0), R(0)};
+      if (k0 >= 1) {
+  #pragma unroll
+        for (int i = 0; i < 3; ++i) nup[i] = nu[(size_t)(k0 - 1) * g.es + ie[i]];
+      }
       for (int k = k0; k < k1; ++k) {
+        R nuk[3] = {R(0), R(0), R(0)};
         if (k < K) {
           const R* row = l1 + (size_t)k * g.es;
           divl1[(size_t)k * g.cs + c] = dif_div<R>(g, row, c);
+  #pragma unroll
+          for (int i = 0; i < 3; ++i) nuk[i] = nu[(size_t)k * g.es + ie[i]];
         }
         const size_t r = (size_t)k * g.cs + c;
-        w_out[r] = dif_w<R>(g, w_in, nu, c, k, cf);
+        w_out[r] = dif_w<R>(g, w_in, nup, nuk, c, k, cf);
+  #pragma unroll
+        for (int i = 0; i < 3; ++i) nup[i] = nuk[i];
       }
     } else {
       const int v = (bx - ncb) * blockDim.x + threadIdx.x;
