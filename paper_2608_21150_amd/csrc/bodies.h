@@ -95,19 +95,38 @@ struct BVc {
     const int kb = args.kb;
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
     if (bx < args.neb) {
-      const int e = bx * blockDim.x + threadIdx.x;
-      if (e >= g.ne) return;
+      // the block's own vn row goes through LDS (double-buffered by level
+      // parity, one barrier per level); the four neighbour edges of the vt
+      // stencil that lie in the block (~87 % for 256 edges) are read there.
+      // Every thread reaches every barrier.
+      __shared__ R s_row[2][kThreads];
+      const int base = bx * blockDim.x;
+      const int e = base + threadIdx.x;
+      const bool in = e < g.ne;
       R* __restrict__ vt = args.vt;
       R* __restrict__ ke = args.ke;
       VtStencil<R> vts;
-      vts.load(g, e);
+      if (in) vts.load(g, e);
       for (int k = k0; k < k1; ++k) {
         const R* row = vn + (size_t)k * g.es;
-        const R a = row[e], b = vts.apply(row, e);
-        const size_t r = (size_t)k * g.es + e;
-        vt[r] = b;
-        ke[r] = R(0.5) * (a * a + b * b);
+        const R a = in ? row[e] : R(0);
+        s_row[k & 1][threadIdx.x] = a;
+        __syncthreads();
+        if (in) {
+          R b = vts.w[0] * a;
+  #pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int l = vts.idx[q] - base;
+            R x = s_row[k & 1][l & (kThreads - 1)];
+            x = (unsigned)l < (unsigned)blockDim.x ? x : row[vts.idx[q]];
+            b += vts.w[1 + q] * x;
+          }
+          const size_t r = (size_t)k * g.es + e;
+          vt[r] = b;
+          ke[r] = R(0.5) * (a * a + b * b);
+        }
       }
+      __syncthreads();  // the next tile of a persistent block reuses s_row
       return;
     }
     if (bx < args.neb + args.nvb) {
@@ -195,8 +214,12 @@ struct BEdge {
     const R* __restrict__ d2 = args.d2;
     const StepCoef cf = args.cf;
     const int kb = args.kb;
-    const int e = bx * blockDim.x + threadIdx.x;
-    if (e >= g.ne) return;
+    // threads past the last edge compute edge 0 and store nothing: every
+    // thread reaches the per-level barriers of the K_e staging below
+    const int base = bx * blockDim.x;
+    const bool in = base + (int)threadIdx.x < g.ne;
+    const int e = in ? base + (int)threadIdx.x : 0;
+    __shared__ R s_ke[2][kThreads];
     const int K = g.K;
     const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
     const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
@@ -226,12 +249,23 @@ struct BEdge {
       const R ie_bot = j < K - 1 ? R(0.5) * (vj + vdn) : vj;
       const R* zr = zeta + (size_t)j * g.vs;
       const R ze = R(0.5) * (zr[v0] + zr[v1]);
+      // K_e of the rhombus edges: from the block's row in LDS where they lie
+      // in the block, else from memory
       const R* kr = ke + (size_t)j * g.es;
-      const R kgrad = ((kr[rh[2]] + kr[rh[3]]) - (kr[rh[0]] + kr[rh[1]])) * third * invd_r;
+      s_ke[j & 1][threadIdx.x] = kr[e];
+      __syncthreads();
+      R kq[4];
+  #pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int l = rh[q] - base;
+        const R x = s_ke[j & 1][l & (kThreads - 1)];
+        kq[q] = (unsigned)l < (unsigned)blockDim.x ? x : kr[rh[q]];
+      }
+      const R kgrad = ((kq[2] + kq[3]) - (kq[0] + kq[1])) * third * invd_r;
       const R wef = (R)(0.5 * (0.5 * (wa0 + wa1) + 0.5 * (wb0 + wb1)));
       // this edge's share of the horizontal advection of w at half level j:
       // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
-      if (j > 0) gw[re] = le * ie_top * (R)(wa1 - wa0);
+      if (j > 0 && in) gw[re] = le * ie_top * (R)(wa1 - wa0);
       const R vt = vtf[re];
       const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
       const size_t rc = (size_t)j * g.cs;
@@ -240,17 +274,20 @@ struct BEdge {
       const R the = (R)(0.5 * (th[rc + c0] + th[rc + c1]));
       const R pgf = (R)cf.cpd * the * gex;
       if (!CORR) {
-        tvn0[re] = tvn;
-        vout[re] = vj + (R)cf.dtau * (tvn - pgf);
+        if (in) {
+          tvn0[re] = tvn;
+          vout[re] = vj + (R)cf.dtau * (tvn - pgf);
+        }
       } else {
         const R dd = (d2[rc + c1] - d2[rc + c0]) * invd_r;
-        vout[re] = vn_now[re] + (R)cf.dtau * ((R)cf.a0 * tvn0[re] + (R)cf.a1 * tvn - pgf) - (R)cf.c4a2 * dd;
+        if (in) vout[re] = vn_now[re] + (R)cf.dtau * ((R)cf.a0 * tvn0[re] + (R)cf.a1 * tvn - pgf) - (R)cf.c4a2 * dd;
       }
       vup = vj;
       vj = vdn;
       wa0 = wb0;
       wa1 = wb1;
     }
+    __syncthreads();  // the next tile of a persistent block reuses s_ke
   }
 };
 
