@@ -94,6 +94,12 @@ __device__ __forceinline__ s4 pack(f4 v) {
   r[3] = (short)to_bf16(v[3]);
   return r;
 }
+// Orders a wave's LDS writes before its later LDS reads of other lanes'
+// entries: LDS executes one wave's instructions in issue order, and the
+// wave barrier keeps the compiler from moving them across.  For LDS rows
+// that only this wave uses.
+__device__ __forceinline__ void wave_lds_sync() { __builtin_amdgcn_wave_barrier(); }
+
 __device__ __forceinline__ float sum16(float v) {
   v += __shfl_xor(v, 1, 16);
   v += __shfl_xor(v, 2, 16);
@@ -137,7 +143,7 @@ __device__ void stage_weights(SW& s, const float* __restrict__ p, bf16* w2n) {
 // Forward of the wave's 64 samples (normalised BF16 features in xs), one
 // 16-row tile at a time; y[st][t] receives the output of row 16 st + 4 q + t
 // (all 16 lanes of a row group hold it).  hs is the wave's 16-row h1 tile.
-// Contains block barriers (every wave of the block calls it).
+// Uses only the wave's own LDS rows.
 __device__ void forward64(const SW& s, const bf16* xs, bf16* hs, float y[4][4]) {
   const int l = threadIdx.x & 63, j = l & 15, q = l >> 4;
 #pragma unroll
@@ -150,7 +156,7 @@ __device__ void forward64(const SW& s, const bf16* xs, bf16* hs, float y[4][4]) 
 #pragma unroll
       for (int t = 0; t < 4; ++t) hs[(4 * q + t) * HS + 16 * nt + j] = to_bf16(gelu(acc[t] + s.b1[16 * nt + j]));
     }
-    __syncthreads();
+    wave_lds_sync();
     float yp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
@@ -162,7 +168,7 @@ __device__ void forward64(const SW& s, const bf16* xs, bf16* hs, float y[4][4]) 
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) y[st][t] = sum16(yp[t]) + s.b3;
-    __syncthreads();
+    wave_lds_sync();
   }
 }
 
@@ -260,7 +266,7 @@ __global__ void __launch_bounds__(128) k_infer(DevGrid g, FeatIn fin, const floa
     }
 #pragma unroll
     for (int i = 0; i < XK; ++i) xs[l * XS + i] = i < NIN ? to_bf16((f[i] - nrm->mean[i]) * nrm->istd[i]) : (bf16)0;
-    __syncthreads();
+    wave_lds_sync();
     float y[4][4];
     forward64(s, xs, hs, y);
 #pragma unroll
@@ -271,7 +277,7 @@ __global__ void __launch_bounds__(128) k_infer(DevGrid g, FeatIn fin, const floa
           const int ee = e0 + 16 * st + 4 * q + t;
           if (ee < g.ne) tout[(size_t)k * g.es + ee] = (R)(y[st][t] * nrm->tstd);
         }
-    __syncthreads();
+    wave_lds_sync();
   }
 }
 
