@@ -152,7 +152,8 @@ typedef struct {
  * DC_EGRID when: an index is out of range; e2c/c2e/e2v/c2e2c disagree; an
  * edge is not in exactly two cells; V - E + C != 2; a length or area <= 0;
  * n_e . (x_c1 - x_c0) <= 0; a vertex has more than 6 edges.  Memory owned by
- * the grid is released by dc_grid_destroy. */
+ * the grid is released by dc_grid_destroy.  DC_EINVAL for counts <= 0 or
+ * n_lev outside [1, 129] (the column solver's limit). */
 dc_status dc_grid_create(const dc_grid_desc *desc, dc_grid **out);
 dc_status dc_grid_info_get(const dc_grid *grid, dc_grid_info *info);
 /* Copy a derived table (see DC_TAB_*) to host_out, which holds n int32. */
