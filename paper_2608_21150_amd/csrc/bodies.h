@@ -662,64 +662,101 @@ struct BCol {
 // diffusion arithmetic shared by the plain kernels and the per-column
 // fallback of the surrogate (identical expressions, identical results)
 // ---------------------------------------------------------------------------
-// first vector Laplacian at edge e: grad(div vn) - gradt(curl vn)
+// Each helper holds the stencil geometry of one entity in registers: a
+// thread loads it once and applies it at every level of its block (the
+// double-precision tables would otherwise be fetched again at each level,
+// since the compiler cannot prove that the stores leave them unchanged).
+//
+// first vector Laplacian at edge e, grad(div vn) - gradt(curl vn), and the
+// Smagorinsky viscosity from the rhombus deformation of the vertex vectors
 template <typename R>
-__device__ __forceinline__ R dif_l1(const DevGrid& g, const R* dr, const R* zr, int e) {
-  const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
-  const int v0 = g.e2c2v[e], v1 = g.e2c2v[g.es + e];
-  const R invd = (R)g.invd[e], invl = (R)g.invl[e];
-  return (dr[c1] - dr[c0]) * invd - (zr[v1] - zr[v0]) * invl;
-}
-// Derivatives of the normal and tangential wind across the rhombus of edge e
-// from the vertex vectors (vx, vy, vz: the three components at one level):
-// d = {dvn/dt, dvt/dt, dvn/dn, dvt/dn}
+struct Edge1Geo {
+  int c0, c1, rv[4];
+  R invd, invl, invlr, n[3], t[3], smag, cap;
+  __device__ __forceinline__ void load_rhombus(const DevGrid& g, int e) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rv[i] = g.e2c2v[i * g.es + e];
+    invl = (R)g.invl[e];
+    invlr = (R)g.invlr[e];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      n[i] = (R)g.nrm[i * g.es + e];
+      t[i] = (R)g.tan[i * g.es + e];
+    }
+  }
+  __device__ __forceinline__ void load(const DevGrid& g, int e, const StepCoef& cf) {
+    load_rhombus(g, e);
+    c0 = g.e2c[e];
+    c1 = g.e2c[g.es + e];
+    invd = (R)g.invd[e];
+    const double ae = g.ae[e];
+    smag = (R)(cf.cs * ae);
+    cap = (R)(ae / (cf.cap * cf.dt));
+  }
+  __device__ __forceinline__ R l1(const R* dr, const R* zr) const {
+    return (dr[c1] - dr[c0]) * invd - (zr[rv[1]] - zr[rv[0]]) * invl;
+  }
+  // derivatives of the normal and tangential wind across the rhombus from the
+  // vertex vectors (vx, vy, vz: the three components at one level):
+  // d = {dvn/dt, dvt/dt, dvn/dn, dvt/dn}
+  __device__ __forceinline__ void rhombus(const R* vx, const R* vy, const R* vz, R d[4]) const {
+    const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
+    const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
+    d[0] = (tx * n[0] + ty * n[1] + tz * n[2]) * invl;
+    d[1] = (tx * t[0] + ty * t[1] + tz * t[2]) * invl;
+    d[2] = (nx * n[0] + ny * n[1] + nz * n[2]) * invlr;
+    d[3] = (nx * t[0] + ny * t[1] + nz * t[2]) * invlr;
+  }
+  __device__ __forceinline__ R nu(const R* vx, const R* vy, const R* vz) const {
+    R d[4];
+    rhombus(vx, vy, vz, d);
+    const R a = d[2] - d[1], b = d[3] + d[0];
+    const R def = sqrt(a * a + b * b);
+    return fmin(smag * def, cap);
+  }
+};
 template <typename R>
 __device__ __forceinline__ void dif_rhombus(const DevGrid& g, const R* vx, const R* vy, const R* vz, int e, R d[4]) {
-  int rv[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) rv[i] = g.e2c2v[i * g.es + e];
-  const R invl = (R)g.invl[e], invlr = (R)g.invlr[e];
-  const R n0 = (R)g.nrm[e], n1 = (R)g.nrm[g.es + e], n2 = (R)g.nrm[2 * g.es + e];
-  const R t0 = (R)g.tan[e], t1 = (R)g.tan[g.es + e], t2 = (R)g.tan[2 * g.es + e];
-  const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
-  const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
-  d[0] = (tx * n0 + ty * n1 + tz * n2) * invl;
-  d[1] = (tx * t0 + ty * t1 + tz * t2) * invl;
-  d[2] = (nx * n0 + ny * n1 + nz * n2) * invlr;
-  d[3] = (nx * t0 + ny * t1 + nz * t2) * invlr;
-}
-// Smagorinsky viscosity at edge e from the rhombus deformation
-template <typename R>
-__device__ __forceinline__ R dif_nu(const DevGrid& g, const R* vx, const R* vy, const R* vz, int e,
-                                    const StepCoef& cf) {
-  R d[4];
-  dif_rhombus<R>(g, vx, vy, vz, e, d);
-  const double ae = g.ae[e];
-  const R smag = (R)(cf.cs * ae);
-  const R cap = (R)(ae / (cf.cap * cf.dt));
-  const R a = d[2] - d[1], b = d[3] + d[0];
-  const R def = sqrt(a * a + b * b);
-  return fmin(smag * def, cap);
+  Edge1Geo<R> q;
+  q.load_rhombus(g, e);
+  q.rhombus(vx, vy, vz, d);
 }
 // divergence at cell c of an edge field row
 template <typename R>
-__device__ __forceinline__ R dif_div(const DevGrid& g, const R* row, int c) {
-  const int i0 = g.c2e[c], i1 = g.c2e[g.cs + c], i2 = g.c2e[2 * g.cs + c];
-  const R k0 = (R)g.kdiv[c], k1 = (R)g.kdiv[g.cs + c], k2 = (R)g.kdiv[2 * g.cs + c];
-  return k0 * row[i0] + k1 * row[i1] + k2 * row[i2];
-}
+struct DivGeo {
+  int ie[3];
+  R kd[3];
+  __device__ __forceinline__ void load(const DevGrid& g, int c) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      ie[i] = g.c2e[i * g.cs + c];
+      kd[i] = (R)g.kdiv[i * g.cs + c];
+    }
+  }
+  __device__ __forceinline__ R apply(const R* row) const { return kd[0] * row[ie[0]] + kd[1] * row[ie[1]] + kd[2] * row[ie[2]]; }
+};
 // relative vorticity at vertex v of an edge field row
 template <typename R>
-__device__ __forceinline__ R dif_curl(const DevGrid& g, const R* row, int v) {
-  R z = (R)g.kcurl[v] * row[g.v2e[v]];
+struct CurlGeo {
+  int ie[6];
+  R kc[6];
+  __device__ __forceinline__ void load(const DevGrid& g, int v) {
 #pragma unroll
-  for (int s = 1; s < 6; ++s) z += (R)g.kcurl[s * g.vs + v] * row[g.v2e[s * g.vs + v]];
-  return z;
-}
+    for (int s = 0; s < 6; ++s) {
+      ie[s] = g.v2e[s * g.vs + v];
+      kc[s] = (R)g.kcurl[s * g.vs + v];
+    }
+  }
+  __device__ __forceinline__ R apply(const R* row) const {
+    R z = kc[0] * row[ie[0]];
+#pragma unroll
+    for (int s = 1; s < 6; ++s) z += kc[s] * row[ie[s]];
+    return z;
+  }
+};
 // second Laplacian at edge e from div(L1) at cells and curl(L1) at vertices
 template <typename R>
-__device__ __forceinline__ R dif_l2(const DevGrid& g, R dl1_c0, R dl1_c1, R cl1_v0, R cl1_v1, int e) {
-  const R invd = (R)g.invd[e], invl = (R)g.invl[e];
+__device__ __forceinline__ R dif_l2(R invd, R invl, R dl1_c0, R dl1_c1, R cl1_v0, R cl1_v1) {
   return (dl1_c1 - dl1_c0) * invd - (cl1_v1 - cl1_v0) * invl;
 }
 template <typename R>
@@ -728,10 +765,22 @@ __device__ __forceinline__ R dif_update(R vn, R dt, R nu, R l1, R k4a2, R l2) {
 }
 // w at cell c, half level k after Smagorinsky diffusion with the edge
 // viscosity (na, nb: nu on the cell's three edges at the full levels k-1 and
-// k, averaged to the cell and the half level)
+// k, averaged to the cell and the half level); the cell's neighbours and the
+// weights of the scalar Laplacian are held in registers
+struct LapGeo {
+  int nb[3];
+  double kl[3];
+  __device__ __forceinline__ void load(const DevGrid& g, int c) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      nb[i] = g.c2e2c[i * g.cs + c];
+      kl[i] = g.klap[i * g.cs + c];
+    }
+  }
+};
 template <typename R>
-__device__ __forceinline__ double dif_w(const DevGrid& g, const double* w_in, const R* na, const R* nb, int c, int k,
-                                        const StepCoef& cf) {
+__device__ __forceinline__ double dif_w(const DevGrid& g, const LapGeo& q, const double* w_in, const R* na,
+                                        const R* nb, int c, int k, const StepCoef& cf) {
   const size_t r = (size_t)k * g.cs + c;
   double wn = w_in[r];
   if (cf.diffuse_w && k >= 1 && k <= g.K - 1) {
@@ -742,7 +791,7 @@ __device__ __forceinline__ double dif_w(const DevGrid& g, const double* w_in, co
     const double* wr = w_in + (size_t)k * g.cs;
     double lw = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) lw += g.klap[i * g.cs + c] * (wr[g.c2e2c[i * g.cs + c]] - wn);
+    for (int i = 0; i < 3; ++i) lw += q.kl[i] * (wr[q.nb[i]] - wn);
     wn = wn + cf.dt * (double)nuc * lw;
   }
   return wn;
@@ -852,13 +901,15 @@ struct BDedge1 {
     const int e = bx * blockDim.x + threadIdx.x;
     if (e >= g.ne) return;
     const size_t plane = (size_t)g.K * g.vs;
+    Edge1Geo<R> q;
+    q.load(g, e, cf);
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
     for (int k = k0; k < k1; ++k) {
       const R* dr = dv + (size_t)k * g.cs;
       const R* zr = zeta + (size_t)k * g.vs;
-      l1[(size_t)k * g.es + e] = dif_l1<R>(g, dr, zr, e);
+      l1[(size_t)k * g.es + e] = q.l1(dr, zr);
       const R* vx = vv + (size_t)k * g.vs;
-      nu[(size_t)k * g.es + e] = dif_nu<R>(g, vx, vx + plane, vx + 2 * plane, e, cf);
+      nu[(size_t)k * g.es + e] = q.nu(vx, vx + plane, vx + 2 * plane);
     }
   }
 };
@@ -893,9 +944,11 @@ struct BDcv2 {
     if (bx < ncb) {
       const int c = bx * blockDim.x + threadIdx.x;
       if (c >= g.nc) return;
-      int ie[3];
-  #pragma unroll
-      for (int i = 0; i < 3; ++i) ie[i] = g.c2e[i * g.cs + c];
+      DivGeo<R> dq;
+      dq.load(g, c);
+      LapGeo lq;
+      lq.load(g, c);
+      const int* ie = dq.ie;
       const int k0 = by * kb, k1 = min(K + 1, k0 + kb);
       // nu on the cell's edges at full level k - 1, carried from one half
       // level to the next
@@ -908,29 +961,22 @@ struct BDcv2 {
         R nuk[3] = {R(0), R(0), R(0)};
         if (k < K) {
           const R* row = l1 + (size_t)k * g.es;
-          divl1[(size_t)k * g.cs + c] = dif_div<R>(g, row, c);
+          divl1[(size_t)k * g.cs + c] = dq.apply(row);
   #pragma unroll
           for (int i = 0; i < 3; ++i) nuk[i] = nu[(size_t)k * g.es + ie[i]];
         }
         const size_t r = (size_t)k * g.cs + c;
-        w_out[r] = dif_w<R>(g, w_in, nup, nuk, c, k, cf);
+        w_out[r] = dif_w<R>(g, lq, w_in, nup, nuk, c, k, cf);
   #pragma unroll
         for (int i = 0; i < 3; ++i) nup[i] = nuk[i];
       }
     } else {
       const int v = (bx - ncb) * blockDim.x + threadIdx.x;
       if (v >= g.nv) return;
-      int idx[6];
-      R cc[6];
-  #pragma unroll
-      for (int s = 0; s < 6; ++s) {
-        idx[s] = g.v2e[s * g.vs + v];
-        cc[s] = (R)g.kcurl[s * g.vs + v];
-      }
+      CurlGeo<R> q;
+      q.load(g, v);
       const int k0 = by * kb, k1 = min(K, k0 + kb);
-      for (int k = k0; k < k1; ++k) {
-        curll1[(size_t)k * g.vs + v] = dif_curl<R>(g, l1 + (size_t)k * g.es, v);
-      }
+      for (int k = k0; k < k1; ++k) curll1[(size_t)k * g.vs + v] = q.apply(l1 + (size_t)k * g.es);
     }
   }
 };
@@ -963,11 +1009,12 @@ struct BDedge2 {
     const double ae = g.ae[e];
     const R k4a2 = (R)(cf.k4 * ae * ae);
     const R dt = (R)cf.dt;
+    const R invd = (R)g.invd[e], invl = (R)g.invl[e];
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
     for (int k = k0; k < k1; ++k) {
       const R* dr = divl1 + (size_t)k * g.cs;
       const R* zr = curll1 + (size_t)k * g.vs;
-      const R l2 = dif_l2<R>(g, dr[c0], dr[c1], zr[v0], zr[v1], e);
+      const R l2 = dif_l2<R>(invd, invl, dr[c0], dr[c1], zr[v0], zr[v1]);
       const size_t r = (size_t)k * g.es + e;
       vn[r] = dif_update<R>(vn[r], dt, nu[r], l1[r], k4a2, l2);
     }

@@ -317,10 +317,11 @@ __global__ void __launch_bounds__(256) k_apply(DevGrid g, R* __restrict__ vn, co
     const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
     const double ae = g.ae[e];
     const R k4a2 = (R)(cf.k4 * ae * ae);
+    const R invd = (R)g.invd[e], invl = (R)g.invl[e];
     for (int k = 0; k < g.K; ++k) {
       const R* dr = dl1 + (size_t)k * g.cs;
       const R* zr = cl1 + (size_t)k * g.vs;
-      const R l2 = dif_l2<R>(g, dr[c0], dr[c1], zr[v0], zr[v1], e);
+      const R l2 = dif_l2<R>(invd, invl, dr[c0], dr[c1], zr[v0], zr[v1]);
       const size_t r = (size_t)k * g.es + e;
       vn[r] = dif_update<R>(vn[r], dt, nu[r], l1[r], k4a2, l2);
     }
