@@ -195,7 +195,11 @@ dc_status dc_state_destroy(dc_state *st);
  * every launch of dc_dycore_step (paper, Section 4.3.3: the profile of one
  * substep, launch versus execution).  enable != 0 clears and starts the
  * record, 0 stops it.  dc_state_profile_read synchronises and fills one
- * entry per kernel kind (cap >= 15): name, launches, summed duration. */
+ * entry per kernel kind (cap >= 11), in kernel-id order: name, launches,
+ * summed duration.  dc_state_profile_select limits later records to the
+ * kernels whose bit (1u << kernel id) is set in kernel_mask (0 or all ones:
+ * every kernel), so that one kernel can be timed inside a run with little
+ * disturbance of the others. */
 typedef struct {
   char name[32];
   int64_t calls;
@@ -203,6 +207,23 @@ typedef struct {
 } dc_kernel_stat;
 dc_status dc_state_profile(dc_state *st, int32_t enable);
 dc_status dc_state_profile_read(dc_state *st, dc_kernel_stat *out, int32_t cap, int32_t *n_out);
+dc_status dc_state_profile_select(dc_state *st, uint32_t kernel_mask);
+
+/* Launch tiles.  The stencil kernels run 2-D grids of tiles: a block of
+ * `threads` consecutive entities times `levels` consecutive levels.  Five
+ * families share a tile each: 0 vorticity and kinetic energy, 1 edge
+ * momentum update, 2 diffusion vertex pass, 3 diffusion cell passes,
+ * 4 diffusion edge passes.  No result depends on the tiles.
+ * dc_state_autotune times candidate tiles (64, 128 or 256 threads; the
+ * levels split into 1 to 11 near-equal blocks) with trial steps of
+ * (dt, nsubsteps) on the state's own fields, keeps the fastest per family,
+ * and restores the fields and the buffer parity: later steps give the same
+ * bits as without tuning.  It synchronises, allocates a copy of the five
+ * fields for the duration of the call, and takes about 50 trial steps.
+ * dc_state_tiles writes threads and levels of family t to out[2t], out[2t+1]
+ * (n >= 10). */
+dc_status dc_state_autotune(dc_state *st, double dt, int32_t nsubsteps);
+dc_status dc_state_tiles(const dc_state *st, int32_t *out, int32_t n);
 
 /* Batched ensemble (paper, Section 4.3.3: launch overhead must not show).
  * Members on any grids, sharing precision, n_lev and diffusion mode, and

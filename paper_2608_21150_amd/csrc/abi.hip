@@ -185,6 +185,21 @@ void enqueue_step(dc_state* s, double dt, int nsub) {
   }
 }
 
+// One step with the plain diffusion (or none), whatever the state's mode: the
+// timing trials of the tuner leave the surrogate's flags and counters alone.
+template <typename R>
+void enqueue_trial_step(dc_state* s, double dt, int nsub) {
+  const StepCoef c = make_coef(s, dt, nsub);
+  const bool diffuse = s->diff != DC_DIFF_NONE;
+  enqueue_substeps<R>(s, c, nsub, diffuse);
+  if (diffuse) {
+    const dc_fields& cur = s->buf[s->cur];
+    launch_diffusion<R>(s->d, static_cast<R*>(cur.vn), s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt),
+                        static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
+                        static_cast<R*>(s->zeta), static_cast<R*>(s->vv), c, s->tiles, s->stream, &s->prof);
+  }
+}
+
 dc_status run_diag(dc_state* s, dc_diag* out) {
   const dc_fields& f = s->buf[s->cur];
   if (s->prec == DC_PREC_MIXED)
@@ -509,6 +524,118 @@ dc_status dc_state_profile(dc_state* s, int32_t enable) {
   DC_TRY(hipStreamSynchronize(s->stream));
   s->prof.on = enable != 0;
   s->prof.used = 0;
+  return DC_OK;
+}
+
+dc_status dc_state_profile_select(dc_state* s, uint32_t kernel_mask) {
+  if (!s) return fail(DC_EINVAL, "state is NULL");
+  DC_TRY(hipStreamSynchronize(s->stream));
+  s->prof.mask = kernel_mask == 0 ? ~0u : kernel_mask;
+  return DC_OK;
+}
+
+
+dc_status dc_state_autotune(dc_state* s, double dt, int32_t nsub) {
+  if (!s) return fail(DC_EINVAL, "state is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DC_EINVAL, "dt must be finite and > 0");
+  if (nsub < 1 || nsub > 1000) return fail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
+  DC_TRY(hipStreamSynchronize(s->stream));
+  // the trial steps advance the state: keep a copy of the current fields
+  const int parity = s->cur;
+  void* saved[DC_FIELD_COUNT] = {};
+  size_t bytes[DC_FIELD_COUNT] = {};
+  auto release = [&]() {
+    for (void* p : saved)
+      if (p) (void)hipFree(p);
+  };
+  for (int f = 0; f < DC_FIELD_COUNT; ++f) {
+    dc_field_bytes(s->grid, s->prec, f, &bytes[f]);
+    if (hipMalloc(&saved[f], bytes[f]) != hipSuccess) {
+      saved[f] = nullptr;
+      release();
+      return fail(DC_ENOMEM, "autotune: no memory for the copy of the fields");
+    }
+    if (hipMemcpyAsync(saved[f], field_ptr(s->buf[parity], f), bytes[f], hipMemcpyDeviceToDevice, s->stream) !=
+        hipSuccess) {
+      release();
+      return fail(DC_EHIP, "autotune: copy of the fields failed");
+    }
+  }
+  // candidates: threads x near-equal level blocks
+  const int K = s->grid->h.K;
+  std::vector<Tile> cands;
+  for (int th : {64, 128, 256}) {
+    int last = 0;
+    for (int nby : {1, 2, 3, 4, 5, 6, 8, 11}) {
+      const int kb = (K + nby - 1) / nby;
+      if (kb != last) cands.push_back({th, kb});
+      last = kb;
+    }
+  }
+  static const std::vector<std::vector<int>> uses = {
+      {K_VC_P, K_VC_C}, {K_EDGE_P, K_EDGE_C}, {K_DVERT}, {K_DDIV, K_DCV2}, {K_DEDGE1, K_DEDGE2}};
+  const Tile tile0[T_COUNT] = {s->tiles[0], s->tiles[1], s->tiles[2], s->tiles[3], s->tiles[4]};
+  const bool prof_on = s->prof.on;
+  const unsigned prof_mask = s->prof.mask;
+  std::vector<double> best(T_COUNT, 1e300);
+  std::vector<Tile> best_tile(tile0, tile0 + T_COUNT);
+  hipError_t err = hipSuccess;
+  for (size_t ci = 0; ci < cands.size() && err == hipSuccess; ++ci) {
+    for (int t = 0; t < T_COUNT; ++t) s->tiles[t] = cands[ci];
+    double per[K_COUNT];
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+      s->prof.on = true;
+      s->prof.mask = ~0u;
+      s->prof.used = 0;
+      if (s->prec == DC_PREC_MIXED)
+        enqueue_trial_step<float>(s, dt, nsub);
+      else
+        enqueue_trial_step<double>(s, dt, nsub);
+      s->prof.on = false;
+      err = hipGetLastError();
+      if (err == hipSuccess) err = hipStreamSynchronize(s->stream);
+      double cur[K_COUNT] = {0};
+      for (size_t i = 0; i + 1 < s->prof.used && err == hipSuccess; ++i)
+        if (s->prof.kid[i] >= 0 && s->prof.kid[i + 1] == -1) {
+          float ms = 0.f;
+          err = hipEventElapsedTime(&ms, s->prof.ev[i], s->prof.ev[i + 1]);
+          cur[s->prof.kid[i]] += ms;
+        }
+      for (int k = 0; k < K_COUNT; ++k) per[k] = rep == 0 ? cur[k] : std::min(per[k], cur[k]);
+    }
+    for (int t = 0; t < T_COUNT && err == hipSuccess; ++t) {
+      double sum = 0.0;
+      for (int k : uses[t]) sum += per[k];
+      if (sum < best[t]) {
+        best[t] = sum;
+        best_tile[t] = cands[ci];
+      }
+    }
+  }
+  // restore the fields, the parity and the profiler
+  s->cur = parity;
+  for (int f = 0; f < DC_FIELD_COUNT && err == hipSuccess; ++f)
+    err = hipMemcpyAsync(field_ptr(s->buf[parity], f), saved[f], bytes[f], hipMemcpyDeviceToDevice, s->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(s->stream);
+  release();
+  s->prof.on = prof_on;
+  s->prof.mask = prof_mask;
+  s->prof.used = 0;
+  if (err != hipSuccess) {
+    std::copy(tile0, tile0 + T_COUNT, s->tiles);
+    return fail(DC_EHIP, std::string("autotune trial failed: ") + hipGetErrorString(err));
+  }
+  std::copy(best_tile.begin(), best_tile.end(), s->tiles);
+  return DC_OK;
+}
+
+dc_status dc_state_tiles(const dc_state* s, int32_t* out, int32_t n) {
+  if (!s || !out) return fail(DC_EINVAL, "NULL argument");
+  if (n < 2 * T_COUNT) return fail(DC_EINVAL, "need room for 10 values");
+  for (int t = 0; t < T_COUNT; ++t) {
+    out[2 * t] = s->tiles[t].threads;
+    out[2 * t + 1] = s->tiles[t].kb;
+  }
   return DC_OK;
 }
 

@@ -19,6 +19,8 @@ extern const char* const kKernelNames[K_COUNT];
 // Optional HIP-event timer: mark(id) before a launch, mark(-1) after it.
 struct Prof {
   bool on = false;
+  unsigned mask = ~0u;  // kernels (1u << id) whose launches are recorded
+  bool wants(int id) const { return on && ((mask >> id) & 1u); }
   std::vector<hipEvent_t> ev;
   std::vector<int> kid;
   size_t used = 0;

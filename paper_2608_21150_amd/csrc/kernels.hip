@@ -138,9 +138,10 @@ namespace {
 template <typename B>
 void one(int id, const DevGrid& g, const typename B::Args& a, const Tile* T, hipStream_t s, Prof* prof) {
   const bodies::Geom geo = bodies::geom_of(id, g, T);
-  if (prof) prof->mark(s, id);
+  const bool rec = prof && prof->wants(id);
+  if (rec) prof->mark(s, id);
   bodies::k_one<B><<<dim3(geo.nbx, geo.nby), geo.threads, geo.smem, s>>>(g, a);
-  if (prof) prof->mark(s, -1);
+  if (rec) prof->mark(s, -1);
 }
 
 template <typename R, bool CORR>

@@ -129,19 +129,21 @@ void surrogate_diffusion(dc_state* s, const StepCoef& c);
 void surrogate_free(dc_state* s);
 void surrogate_geometry(dc_state* s);
 
-// Default launch tiles: levels per block so that each launch has a few
-// thousand blocks when the grid is large, one level per block on small grids.
+// Default launch tiles (dc_state_autotune replaces them by measured ones).
+// The levels are split into near-equal blocks: a short last block leaves
+// much of its wave's time unused.  Shapes from timings of the 81920-cell,
+// 65-level grid on one MI355X: thin edge-momentum tiles running deep in the
+// column, wide vorticity and diffusion tiles with a few levels each.
 inline void default_tiles(const HostGrid& h, Tile* t) {
-  auto kb_for = [&](int n, int levels) {
-    const int nbx = (n + 255) / 256;
-    int kb = (int)((long long)levels * nbx / 2048);
-    return std::max(1, std::min(kb, 16));
+  auto kb_of = [&](int nby) {
+    nby = std::max(1, std::min(nby, h.K));
+    return (h.K + nby - 1) / nby;
   };
-  t[T_VC] = {256, kb_for(h.ne + h.nv, h.K)};
-  t[T_EDGE] = {256, kb_for(h.ne, h.K)};
-  t[T_DVERT] = {256, kb_for(h.nv, h.K)};
-  t[T_DCELL] = {256, kb_for(h.nc + h.nv, h.K + 1)};
-  t[T_DEDGE] = {256, kb_for(h.ne, h.K)};
+  t[T_VC] = {256, kb_of(6)};
+  t[T_EDGE] = {64, kb_of(2)};
+  t[T_DVERT] = {256, kb_of(3)};
+  t[T_DCELL] = {256, kb_of(11)};
+  t[T_DEDGE] = {128, kb_of(5)};
 }
 
 }  // namespace dc

@@ -19,6 +19,10 @@ DC_OK, DC_EINVAL, DC_EGRID, DC_EHIP, DC_ENOMEM, DC_ENONFINITE, DC_EBUSY, DC_ESTA
 PREC = {"fp64": 0, "mixed": 1}
 DIFF = {"plain": 0, "surrogate": 1, "none": 2}
 FIELDS = ("vn", "w", "rho", "exner", "theta_v")
+# kernel ids of the per-kernel profile, and the five launch-tile families
+KERNELS = ("vort_ke_pred", "edge_pred", "column_pred", "vort_ke_corr", "edge_corr", "column_corr", "diff_vertex",
+           "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2")
+TILE_FAMILIES = ("vort_ke", "edge", "diff_vertex", "diff_cell", "diff_edge")
 TABLES = ("e2c", "c2e", "e2v", "c2e2c", "c2v", "v2e", "v2c", "e2c2e", "e2c2v", "perm_cell", "perm_edge", "perm_vert")
 
 _p = ctypes.c_void_p
@@ -124,6 +128,9 @@ def _load():
         "dc_diag_conservation": (ctypes.c_int, [_p, ctypes.POINTER(Diag)]),
         "dc_state_destroy": (ctypes.c_int, [_p]),
         "dc_state_profile": (ctypes.c_int, [_p, ctypes.c_int32]),
+        "dc_state_profile_select": (ctypes.c_int, [_p, ctypes.c_uint32]),
+        "dc_state_autotune": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
+        "dc_state_tiles": (ctypes.c_int, [_p, _i32p, ctypes.c_int32]),
         "dc_state_profile_read": (ctypes.c_int, [_p, ctypes.POINTER(KernelStat), ctypes.c_int32,
                                                  ctypes.POINTER(ctypes.c_int32)]),
         "dc_ensemble_create": (ctypes.c_int, [ctypes.POINTER(_p), ctypes.c_int32, ctypes.POINTER(_p)]),
@@ -325,6 +332,23 @@ class State:
 
     def profile(self, enable: bool):
         check(lib.dc_state_profile(self.handle, 1 if enable else 0))
+
+    def profile_select(self, kernels=None):
+        """Record only the named kernels (names as profile_read reports them); None: all."""
+        mask = 0
+        if kernels is not None:
+            for k in kernels:
+                mask |= 1 << KERNELS.index(k)
+        check(lib.dc_state_profile_select(self.handle, mask))
+
+    def autotune(self, dt: float, nsub: int):
+        """Time candidate launch tiles with trial steps; the state's fields are restored."""
+        check(lib.dc_state_autotune(self.handle, dt, nsub))
+
+    def tiles(self) -> dict:
+        out = np.zeros(10, dtype=np.int32)
+        check(lib.dc_state_tiles(self.handle, out.ctypes.data_as(_i32p), out.size))
+        return {name: (int(out[2 * i]), int(out[2 * i + 1])) for i, name in enumerate(TILE_FAMILIES)}
 
     def profile_read(self) -> dict:
         arr = (KernelStat * 32)()
