@@ -322,11 +322,11 @@ struct ColArgs {
 // three edge terms l_e vn_ie (w_c1 - w_c0) of the cell (gw, over A_c), vertical
 // part from the column's own w at half levels k-1, k, k+1 (w_up, w_k, w_dn).
 template <typename R>
-__device__ __forceinline__ double col_tw(const DevGrid& g, const R* __restrict__ gw, double w_up, double w_k,
+__device__ __forceinline__ double col_tw(const R* gw, const double* vert, int K1, int es, double w_up, double w_k,
                                          double w_dn, int k, const int* ie, R inv_area) {
-  const R* gr = gw + (size_t)k * g.es;
+  const R* gr = gw + (size_t)k * es;
   const R hs = (gr[ie[0]] + gr[ie[1]] + gr[ie[2]]) * inv_area;
-  const double dwdz = (w_up - w_dn) * vt_row(g, VT_IDZC2)[k];
+  const double dwdz = (w_up - w_dn) * vert[VT_IDZC2 * K1 + k];
   return (double)(R(-0.5) * hs - (R)(w_k * dwdz));
 }
 
@@ -337,27 +337,26 @@ struct ColLev {
   double ric, atil, gam, zth;      // half level j
 };
 
-__device__ __forceinline__ void col_load(const DevGrid& g, const double* __restrict__ rho,
-                                         const double* __restrict__ th, const double* __restrict__ ex, int j, int c,
-                                         ColLev& L) {
-  const size_t r = (size_t)j * g.cs + c;
+__device__ __forceinline__ void col_load(const double* rho, const double* th, const double* ex, const double* vert,
+                                         int K1, int cs, int j, int c, ColLev& L) {
+  const size_t r = (size_t)j * cs + c;
   L.rho = rho[r];
   L.th = th[r];
   L.ex = ex[r];
-  L.thp = L.th - vt_row(g, VT_THREF)[j];
-  L.exp_ = L.ex - vt_row(g, VT_EXREF)[j];
+  L.thp = L.th - vert[VT_THREF * K1 + j];
+  L.exp_ = L.ex - vert[VT_EXREF * K1 + j];
 }
 
 // half-level quantities of level b (= j1) from full levels j1-1 (a) and j1 (b)
-__device__ __forceinline__ void col_half(const DevGrid& g, const ColLev& a, ColLev& b, int j1, double dtau,
+__device__ __forceinline__ void col_half(const double* vert, int K1, const ColLev& a, ColLev& b, int j1, double dtau,
                                          double cpd, double eta) {
   b.ric = 0.5 * (a.rho + b.rho);
   const double thp_ic = 0.5 * (a.thp + b.thp);
-  const double th_ic = vt_row(g, VT_THREFIC)[j1] + thp_ic;
+  const double th_ic = vert[VT_THREFIC * K1 + j1] + thp_ic;
   b.atil = th_ic * b.ric;
-  const double idzh = vt_row(g, VT_IDZH)[j1];
+  const double idzh = vert[VT_IDZH * K1 + j1];
   b.gam = dtau * cpd * eta * th_ic * idzh;
-  b.zth = (1.0 - eta) * th_ic * (a.exp_ - b.exp_) * idzh + thp_ic * vt_row(g, VT_DEXREFIC)[j1];
+  b.zth = (1.0 - eta) * th_ic * (a.exp_ - b.exp_) * idzh + thp_ic * vert[VT_DEXREFIC * K1 + j1];
 }
 
 template <typename R>
@@ -372,9 +371,22 @@ struct BCol {
   using Args = ColPhaseArgs<R>;
   static constexpr int kThreads = 512;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
-    const ColArgs<R> a = args.a;
-    const StepCoef cf = args.cf;
-    const int P = args.P;
+    const ColArgs<R>& a = args.a;
+    body(g, args.cf, args.P, bx, g.vert, g.tau, a.w, a.rho, a.ex, a.th, a.gw, a.vnf, a.tw0, a.dv_out, a.ws, a.w_out,
+         a.rho_out, a.ex_out, a.th_out);
+  }
+  // The fields as restrict parameters: the compiler may then move the loads
+  // of later levels above the stores of earlier ones (no buffer is both read
+  // and written by one launch).
+  __device__ __forceinline__ static void body(const DevGrid& g, const StepCoef cf, const int P, const int bx,
+                                              const double* __restrict__ vert, const double* __restrict__ tau,
+                                              const double* __restrict__ pw, const double* __restrict__ prho,
+                                              const double* __restrict__ pex, const double* __restrict__ pth,
+                                              const R* __restrict__ pgw, const R* __restrict__ pvn,
+                                              double* __restrict__ ptw0, R* __restrict__ pdv,
+                                              const double* __restrict__ pws, double* __restrict__ pw_out,
+                                              double* __restrict__ prho_out, double* __restrict__ pex_out,
+                                              double* __restrict__ pth_out) {
     // LDS: [6][P][64] interface system; s_stg: each wave's row of rho and
     // theta_v at its current level (neighbour gathers inside the tile)
     extern __shared__ double s_red[];
@@ -393,7 +405,8 @@ struct BCol {
     const int n = base + (p < extra ? 1 : 0);
     const int s = 1 + p * base + min(p, extra);
     const int h = s - 1;  // full level above the first row (halo; chunk 0 owns it)
-    const double* idzf = vt_row(g, VT_IDZF);
+    const int K1 = K + 1;
+    const double* idzf = vert + VT_IDZF * K1;
     const double eta = cf.eta, dtau = cf.dtau, cpd = cf.cpd, oneme = 1.0 - eta;
     int ie[3], nb[3];
     double kd[3];
@@ -410,16 +423,16 @@ struct BCol {
     double drxv[LM + 1], dxxv[LM + 1];
 
     ColLev cur;
-    col_load(g, a.rho, a.th, a.ex, h, c, cur);
-    cur.w = a.w[(size_t)h * cs + c];
-    cur.ws = CORR ? a.ws[(size_t)h * cs + c] : 0.0;
+    col_load(prho, pth, pex, vert, K1, cs, h, c, cur);
+    cur.w = pw[(size_t)h * cs + c];
+    cur.ws = CORR ? pws[(size_t)h * cs + c] : 0.0;
     double w_up = 0.0, ws_up = 0.0;
     if (h >= 1) {
       ColLev up;
-      col_load(g, a.rho, a.th, a.ex, h - 1, c, up);
-      col_half(g, up, cur, h, dtau, cpd, eta);
-      w_up = a.w[(size_t)(h - 1) * cs + c];
-      if (CORR) ws_up = a.ws[(size_t)(h - 1) * cs + c];
+      col_load(prho, pth, pex, vert, K1, cs, h - 1, c, up);
+      col_half(vert, K1, up, cur, h, dtau, cpd, eta);
+      w_up = pw[(size_t)(h - 1) * cs + c];
+      if (CORR) ws_up = pws[(size_t)(h - 1) * cs + c];
     } else {
       cur.ric = cur.rho;
       cur.atil = 0.0;
@@ -433,14 +446,14 @@ struct BCol {
         const int j = h + i;
         ColLev nx;
         if (j + 1 < K) {
-          col_load(g, a.rho, a.th, a.ex, j + 1, c, nx);
-          col_half(g, cur, nx, j + 1, dtau, cpd, eta);
-          nx.w = a.w[(size_t)(j + 1) * cs + c];
-          nx.ws = CORR ? a.ws[(size_t)(j + 1) * cs + c] : 0.0;
+          col_load(prho, pth, pex, vert, K1, cs, j + 1, c, nx);
+          col_half(vert, K1, cur, nx, j + 1, dtau, cpd, eta);
+          nx.w = pw[(size_t)(j + 1) * cs + c];
+          nx.ws = CORR ? pws[(size_t)(j + 1) * cs + c] : 0.0;
         } else {
           nx.ric = cur.rho;
           nx.atil = 0.0;
-          nx.w = a.w[(size_t)K * cs + c];
+          nx.w = pw[(size_t)K * cs + c];
           nx.ws = 0.0;
         }
         // mass and theta fluxes, explicit parts at full level j; neighbour
@@ -448,9 +461,9 @@ struct BCol {
         // rows through LDS, the others from memory
         double dm = 0.0, dth = 0.0;
         {
-          const R* vr = a.vnf + (size_t)j * g.es;
-          const double* rr = a.rho + (size_t)j * cs;
-          const double* tr = a.th + (size_t)j * cs;
+          const R* vr = pvn + (size_t)j * g.es;
+          const double* rr = prho + (size_t)j * cs;
+          const double* tr = pth + (size_t)j * cs;
           s_stg[p][0][cl] = cur.rho;
           s_stg[p][1][cl] = cur.th;
           __builtin_amdgcn_wave_barrier();
@@ -478,7 +491,7 @@ struct BCol {
           // predictor: divergence of vn* for the corrector's damping (each
           // full level is stored by the chunk that owns it)
           if (!CORR && ok && (i >= 1 || p == 0))
-            a.dv_out[(size_t)j * cs + c] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
+            pdv[(size_t)j * cs + c] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
         }
         const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
         const double beta = b * idzf[j];
@@ -491,10 +504,10 @@ struct BCol {
           // row of half level j, then one step of the down sweep
           double tw;
           if (CORR) {
-            tw = cf.a0 * a.tw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(g, a.gw, ws_up, cur.ws, nx.ws, j, ie, inv_area);
+            tw = cf.a0 * ptw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(pgw, vert, K1, g.es, ws_up, cur.ws, nx.ws, j, ie, inv_area);
           } else {
-            tw = col_tw<R>(g, a.gw, w_up, cur.w, nx.w, j, ie, inv_area);
-            if (ok) a.tw0[(size_t)j * cs + c] = tw;
+            tw = col_tw<R>(pgw, vert, K1, g.es, w_up, cur.w, nx.w, j, ie, inv_area);
+            if (ok) ptw0[(size_t)j * cs + c] = tw;
           }
           const double wx = cur.w + dtau * (tw - cpd * cur.zth);
           const double A = -cur.gam * beta_p * (eta * atil_p);
@@ -588,28 +601,28 @@ struct BCol {
     // (row i of the chunk is half level s + i; w*(h) of the chunk above is
     // needed only by chunk 0, where it is the w = 0 boundary)
     const int e = s + n;
-    const double w_below = (e < K) ? xb / (1.0 + dtau * g.tau[e]) : 0.0;
+    const double w_below = (e < K) ? xb / (1.0 + dtau * tau[e]) : 0.0;
     if (!CORR) {
   #pragma unroll
       for (int i = 0; i < LM; ++i) {
         if (i < n && ok) {
           const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
-          a.w_out[(size_t)(s + i) * cs + c] = x / (1.0 + dtau * g.tau[s + i]);
+          pw_out[(size_t)(s + i) * cs + c] = x / (1.0 + dtau * tau[s + i]);
         }
       }
     }
-    if (ok && p == 0) a.w_out[c] = 0.0;
-    if (ok && p == P - 1) a.w_out[(size_t)K * cs + c] = 0.0;
+    if (ok && p == 0) pw_out[c] = 0.0;
+    if (ok && p == P - 1) pw_out[(size_t)K * cs + c] = 0.0;
 
     // ---- corrector: w*, and increment updates of rho, exner, theta_v at
     // full levels h..h+n (level h only in chunk 0) ----
     if (CORR) {
       ColLev lv;
-      col_load(g, a.rho, a.th, a.ex, h, c, lv);
+      col_load(prho, pth, pex, vert, K1, cs, h, c, lv);
       if (h >= 1) {
         ColLev up;
-        col_load(g, a.rho, a.th, a.ex, h - 1, c, up);
-        col_half(g, up, lv, h, dtau, cpd, eta);
+        col_load(prho, pth, pex, vert, K1, cs, h - 1, c, up);
+        col_half(vert, K1, up, lv, h, dtau, cpd, eta);
       } else {
         lv.ric = lv.rho;
         lv.atil = 0.0;
@@ -622,13 +635,13 @@ struct BCol {
           double w1 = w_below;
           if (i < n) {
             const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
-            w1 = x / (1.0 + dtau * g.tau[s + i]);
-            if (ok) a.w_out[(size_t)(s + i) * cs + c] = w1;
+            w1 = x / (1.0 + dtau * tau[s + i]);
+            if (ok) pw_out[(size_t)(s + i) * cs + c] = w1;
           }
           ColLev nx;
           if (j + 1 < K) {
-            col_load(g, a.rho, a.th, a.ex, j + 1, c, nx);
-            col_half(g, lv, nx, j + 1, dtau, cpd, eta);
+            col_load(prho, pth, pex, vert, K1, cs, j + 1, c, nx);
+            col_half(vert, K1, lv, nx, j + 1, dtau, cpd, eta);
           } else {
             nx.ric = lv.rho;
             nx.atil = 0.0;
@@ -641,9 +654,9 @@ struct BCol {
             const double rho_new = lv.rho + drho;
             if (ok) {
               const size_t r = (size_t)j * cs + c;
-              a.rho_out[r] = rho_new;
-              a.ex_out[r] = lv.ex + dex;
-              a.th_out[r] = lv.th + lv.th * (lv.rho * cf.cvd_rd * dex - drho * lv.ex) / (lv.ex * rho_new);
+              prho_out[r] = rho_new;
+              pex_out[r] = lv.ex + dex;
+              pth_out[r] = lv.th + lv.th * (lv.rho * cf.cvd_rd * dex - drho * lv.ex) / (lv.ex * rho_new);
             }
           }
           w0 = w1;
