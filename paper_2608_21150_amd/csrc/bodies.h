@@ -387,8 +387,9 @@ struct BCol {
                                               const double* __restrict__ pws, double* __restrict__ pw_out,
                                               double* __restrict__ prho_out, double* __restrict__ pex_out,
                                               double* __restrict__ pth_out) {
-    // LDS: [6][P][64] interface system; s_stg: each wave's row of rho and
-    // theta_v at its current level (neighbour gathers inside the tile)
+    // LDS: [6][P][64] interface system; s_stg (corrector): each wave's row
+    // of rho and theta_v at its current level (neighbour gathers inside the
+    // tile)
     extern __shared__ double s_red[];
     __shared__ double s_stg[8][2][64];
     const int K = g.K, cs = g.cs;
@@ -456,30 +457,41 @@ struct BCol {
           nx.w = pw[(size_t)K * cs + c];
           nx.ws = 0.0;
         }
-        // mass and theta fluxes, explicit parts at full level j; neighbour
-        // rho, theta_v inside the 64-column tile come from the other lanes'
-        // rows through LDS, the others from memory
+        // mass and theta fluxes, explicit parts at full level j.  Neighbour
+        // rho, theta_v: the corrector takes those inside the 64-column tile
+        // from the other lanes' rows through LDS, the others from memory;
+        // the predictor reads them all from memory (the tile's rows were
+        // just read by the other lanes, so mostly from cache), which measured
+        // faster there
         double dm = 0.0, dth = 0.0;
         {
           const R* vr = pvn + (size_t)j * g.es;
           const double* rr = prho + (size_t)j * cs;
           const double* tr = pth + (size_t)j * cs;
-          s_stg[p][0][cl] = cur.rho;
-          s_stg[p][1][cl] = cur.th;
-          __builtin_amdgcn_wave_barrier();
+          if (CORR) {
+            s_stg[p][0][cl] = cur.rho;
+            s_stg[p][1][cl] = cur.th;
+            __builtin_amdgcn_wave_barrier();
+          }
           R vq[3];
   #pragma unroll
           for (int q = 0; q < 3; ++q) {
             vq[q] = vr[ie[q]];
-            // the LDS read is unconditional (masked index), the memory read
-            // only for neighbours outside the tile (written as selects: an
-            // if-statement form makes the gfx950 backend fail machine
-            // verification on the corrector)
-            const int lq = nb[q] - bx * 64;
-            double rn = s_stg[p][0][lq & 63];
-            double tn = s_stg[p][1][lq & 63];
-            rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
-            tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
+            double rn, tn;
+            if (CORR) {
+              // the LDS read is unconditional (masked index), the memory
+              // read only for neighbours outside the tile (written as
+              // selects: an if-statement form makes the gfx950 backend fail
+              // machine verification)
+              const int lq = nb[q] - bx * 64;
+              rn = s_stg[p][0][lq & 63];
+              tn = s_stg[p][1][lq & 63];
+              rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
+              tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
+            } else {
+              rn = rr[nb[q]];
+              tn = tr[nb[q]];
+            }
             const R rho_e = (R)(0.5 * (cur.rho + rn));
             const R th_e = (R)(0.5 * (cur.th + tn));
             const R fm = rho_e * vq[q];
@@ -487,7 +499,7 @@ struct BCol {
             dm += kd[q] * (double)fm;
             dth += kd[q] * (double)ft;
           }
-          __builtin_amdgcn_wave_barrier();
+          if (CORR) __builtin_amdgcn_wave_barrier();
           // predictor: divergence of vn* for the corrector's damping (each
           // full level is stored by the chunk that owns it)
           if (!CORR && ok && (i >= 1 || p == 0))
