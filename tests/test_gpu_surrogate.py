@@ -217,6 +217,34 @@ def test_out_of_range_column_falls_back():
     G.close()
 
 
+def test_autotune_leaves_surrogate_state_alone():
+    """The tuner's trial steps use the plain diffusion and restore the fields:
+    the surrogate's judge flags and counters, and every later step, are those
+    of an untuned state."""
+    g0, S, vert = small_state(seed=16)
+    G = D.Grid(g0, vert)
+    net = D.Mlp(3)
+    a = D.State(G, diffusion="surrogate")
+    b = D.State(G, diffusion="surrogate")
+    for st in (a, b):
+        st.write(S)
+        st.set_mlp(net, threshold=1e-3, judge_every=2)
+        st.step(DT, NSUB)  # a judge step: sets the per-column flags
+    a.autotune(DT, NSUB)
+    assert a.surrogate_stats() == b.surrogate_stats()
+    for _ in range(3):
+        a.step(DT, NSUB)
+        b.step(DT, NSUB)
+    x, y = a.read(), b.read()
+    for name in FIELDS:
+        assert np.array_equal(x[name], y[name]), name
+    assert a.surrogate_stats() == b.surrogate_stats()
+    a.close()
+    b.close()
+    net.close()
+    G.close()
+
+
 def test_fit_norm_keeps_tiny_scales():
     """Feature scales span many orders of magnitude (div L1 ~ 1e-17 on a
     global grid): each gets its own scale, flow features and the target a
