@@ -399,7 +399,11 @@ struct BCol {
     const int cl = threadIdx.x & 63, p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c0 = bx * 64 + cl;
     const bool ok = c0 < g.nc;
-    const int c = ok ? c0 : 0;  // padding lanes compute column 0 and store nothing
+    // padding lanes (c0 >= nc, still inside the padded row) compute column 0
+    // and store it into their own padding entry, which nothing reads: the
+    // stores need no branch, and the loads of later levels may be issued
+    // above them
+    const int c = ok ? c0 : 0;
     // rows (half levels 1..K-1) of this chunk: [s, s + n)
     const int nrow = K - 1;
     const int base = nrow / P, extra = nrow - base * P;
@@ -445,16 +449,18 @@ struct BCol {
     for (int i = 0; i <= LM; ++i) {
       if (i <= n) {
         const int j = h + i;
+        // the level below, clamped at the bottom (no branch: the last full
+        // level takes its own values and then overrides them)
+        const bool bottom = j + 1 >= K;
+        const int jn = bottom ? K - 1 : j + 1;
         ColLev nx;
-        if (j + 1 < K) {
-          col_load(prho, pth, pex, vert, K1, cs, j + 1, c, nx);
-          col_half(vert, K1, cur, nx, j + 1, dtau, cpd, eta);
-          nx.w = pw[(size_t)(j + 1) * cs + c];
-          nx.ws = CORR ? pws[(size_t)(j + 1) * cs + c] : 0.0;
-        } else {
+        col_load(prho, pth, pex, vert, K1, cs, jn, c, nx);
+        col_half(vert, K1, cur, nx, jn, dtau, cpd, eta);
+        nx.w = pw[(size_t)(j + 1) * cs + c];
+        nx.ws = CORR ? pws[(size_t)(j + 1) * cs + c] : 0.0;
+        if (bottom) {
           nx.ric = cur.rho;
           nx.atil = 0.0;
-          nx.w = pw[(size_t)K * cs + c];
           nx.ws = 0.0;
         }
         // mass and theta fluxes, explicit parts at full level j.  Neighbour
@@ -502,8 +508,8 @@ struct BCol {
           if (CORR) __builtin_amdgcn_wave_barrier();
           // predictor: divergence of vn* for the corrector's damping (each
           // full level is stored by the chunk that owns it)
-          if (!CORR && ok && (i >= 1 || p == 0))
-            pdv[(size_t)j * cs + c] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
+          // (level h of chunk p > 0 is also stored by chunk p - 1: the same value)
+          if (!CORR) pdv[(size_t)j * cs + c0] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
         }
         const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
         const double beta = b * idzf[j];
@@ -519,7 +525,7 @@ struct BCol {
             tw = cf.a0 * ptw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(pgw, vert, K1, g.es, ws_up, cur.ws, nx.ws, j, ie, inv_area);
           } else {
             tw = col_tw<R>(pgw, vert, K1, g.es, w_up, cur.w, nx.w, j, ie, inv_area);
-            if (ok) ptw0[(size_t)j * cs + c] = tw;
+            ptw0[(size_t)j * cs + c0] = tw;
           }
           const double wx = cur.w + dtau * (tw - cpd * cur.zth);
           const double A = -cur.gam * beta_p * (eta * atil_p);
@@ -617,9 +623,9 @@ struct BCol {
     if (!CORR) {
   #pragma unroll
       for (int i = 0; i < LM; ++i) {
-        if (i < n && ok) {
+        if (i < n) {
           const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
-          pw_out[(size_t)(s + i) * cs + c] = x / (1.0 + dtau * tau[s + i]);
+          pw_out[(size_t)(s + i) * cs + c0] = x / (1.0 + dtau * tau[s + i]);
         }
       }
     }
@@ -648,13 +654,14 @@ struct BCol {
           if (i < n) {
             const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
             w1 = x / (1.0 + dtau * tau[s + i]);
-            if (ok) pw_out[(size_t)(s + i) * cs + c] = w1;
+            pw_out[(size_t)(s + i) * cs + c0] = w1;
           }
+          const bool bottom = j + 1 >= K;
+          const int jn = bottom ? K - 1 : j + 1;
           ColLev nx;
-          if (j + 1 < K) {
-            col_load(prho, pth, pex, vert, K1, cs, j + 1, c, nx);
-            col_half(vert, K1, lv, nx, j + 1, dtau, cpd, eta);
-          } else {
+          col_load(prho, pth, pex, vert, K1, cs, jn, c, nx);
+          col_half(vert, K1, lv, nx, jn, dtau, cpd, eta);
+          if (bottom) {
             nx.ric = lv.rho;
             nx.atil = 0.0;
           }
@@ -664,8 +671,8 @@ struct BCol {
             const double drho = drxv[i] - dtau * eta * (lv.ric * w0 - nx.ric * w1) * idzf[j];
             const double dex = dxxv[i] - beta * (eta * lv.atil * w0 - eta * nx.atil * w1);
             const double rho_new = lv.rho + drho;
-            if (ok) {
-              const size_t r = (size_t)j * cs + c;
+            {
+              const size_t r = (size_t)j * cs + c0;
               prho_out[r] = rho_new;
               pex_out[r] = lv.ex + dex;
               pth_out[r] = lv.th + lv.th * (lv.rho * cf.cvd_rd * dex - drho * lv.ex) / (lv.ex * rho_new);
