@@ -133,7 +133,9 @@ typedef struct {
 /* Device pointers of the five prognostic fields, [level][entity] padded.
  * FP64 mode: all double.  Mixed mode: vn float, the others double.
  * vn [K][edge_stride], w [K+1][cell_stride], rho/exner/theta_v [K][cell_stride].
- * Every pointer must be 256-byte aligned. */
+ * Every pointer must be 256-byte aligned.  The padding entries of each level
+ * (entities n .. stride-1) belong to the library: a step may write them and
+ * no result depends on them. */
 typedef struct { void *vn, *w, *rho, *exner, *theta_v; } dc_fields;
 
 enum { DC_FIELD_VN = 0, DC_FIELD_W, DC_FIELD_RHO, DC_FIELD_EXNER, DC_FIELD_THETA_V, DC_FIELD_COUNT };
