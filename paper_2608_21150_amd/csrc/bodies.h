@@ -444,6 +444,15 @@ struct BCol {
       cur.gam = 0.0;
       cur.zth = 0.0;
     }
+    // corrector with chunks of up to 12 rows: the full levels' rho, theta_v,
+    // exner stay in registers for the increment updates after the solve
+    // instead of being read again (16-row chunks would spill heavily)
+    constexpr bool kKeep = CORR && LM <= 12;
+    double sv_r[LM + 2], sv_t[LM + 2], sv_e[LM + 2];
+    const double ric0 = cur.ric, atil0 = cur.atil;
+    sv_r[0] = cur.rho;
+    sv_t[0] = cur.th;
+    sv_e[0] = cur.ex;
     double beta_p = 0.0, e_p = 0.0, atil_p = 0.0;
   #pragma unroll
     for (int i = 0; i <= LM; ++i) {
@@ -463,6 +472,9 @@ struct BCol {
           nx.atil = 0.0;
           nx.ws = 0.0;
         }
+        sv_r[i + 1] = nx.rho;
+        sv_t[i + 1] = nx.th;
+        sv_e[i + 1] = nx.ex;
         // mass and theta fluxes, explicit parts at full level j.  Neighbour
         // rho, theta_v: the corrector takes those inside the 64-column tile
         // from the other lanes' rows through LDS, the others from memory;
@@ -636,14 +648,24 @@ struct BCol {
     // full levels h..h+n (level h only in chunk 0) ----
     if (CORR) {
       ColLev lv;
-      col_load(prho, pth, pex, vert, K1, cs, h, c, lv);
-      if (h >= 1) {
-        ColLev up;
-        col_load(prho, pth, pex, vert, K1, cs, h - 1, c, up);
-        col_half(vert, K1, up, lv, h, dtau, cpd, eta);
+      if (kKeep) {
+        lv.rho = sv_r[0];
+        lv.th = sv_t[0];
+        lv.ex = sv_e[0];
+        lv.thp = lv.th - vert[VT_THREF * K1 + h];
+        lv.exp_ = lv.ex - vert[VT_EXREF * K1 + h];
+        lv.ric = ric0;
+        lv.atil = atil0;
       } else {
-        lv.ric = lv.rho;
-        lv.atil = 0.0;
+        col_load(prho, pth, pex, vert, K1, cs, h, c, lv);
+        if (h >= 1) {
+          ColLev up;
+          col_load(prho, pth, pex, vert, K1, cs, h - 1, c, up);
+          col_half(vert, K1, up, lv, h, dtau, cpd, eta);
+        } else {
+          lv.ric = lv.rho;
+          lv.atil = 0.0;
+        }
       }
       double w0 = 0.0;  // w* at half level h (used by chunk 0 only: the top boundary)
   #pragma unroll
@@ -659,7 +681,15 @@ struct BCol {
           const bool bottom = j + 1 >= K;
           const int jn = bottom ? K - 1 : j + 1;
           ColLev nx;
-          col_load(prho, pth, pex, vert, K1, cs, jn, c, nx);
+          if (kKeep) {
+            nx.rho = sv_r[i + 1];
+            nx.th = sv_t[i + 1];
+            nx.ex = sv_e[i + 1];
+            nx.thp = nx.th - vert[VT_THREF * K1 + jn];
+            nx.exp_ = nx.ex - vert[VT_EXREF * K1 + jn];
+          } else {
+            col_load(prho, pth, pex, vert, K1, cs, jn, c, nx);
+          }
           col_half(vert, K1, lv, nx, jn, dtau, cpd, eta);
           if (bottom) {
             nx.ric = lv.rho;
