@@ -174,7 +174,10 @@ dc_status dc_state_workspace_bytes(const dc_grid *grid, dc_precision prec, dc_di
  * by the library; keep them alive until dc_state_destroy).  bufA holds the
  * initial state; each substep writes the other buffer set and flips.
  * stream: a hipStream_t (NULL = the null stream); all work is enqueued
- * there asynchronously. */
+ * there asynchronously.  The workspace belongs to the state until
+ * dc_state_destroy: besides the step's scratch fields it holds per-state
+ * tables written here (Coriolis parameter, sponge profile), so the caller
+ * must not write it. */
 dc_status dc_state_create(const dc_grid *grid, const dc_params *params, dc_precision prec,
                           dc_diffusion diff, dc_fields bufA, dc_fields bufB, void *workspace,
                           size_t workspace_bytes, void *stream, dc_state **out);

@@ -11,7 +11,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_2608_21150_amd import dycore as D  # noqa: E402
-from synth import build_workload  # noqa: E402
+from synth import build_workload, initial_state, make_grid  # noqa: E402
 
 FIELDS = ("vn", "w", "rho", "exner", "theta_v")
 
@@ -67,4 +67,40 @@ def test_profile_select_records_one_kernel():
     with pytest.raises(D.DycoreError):
         st.autotune(-1.0, 2)
     st.close()
+    G.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_padding_contents_do_not_matter(precision):
+    """Padding entries of the field buffers belong to the library: NaN in all
+    of them, in both buffer sets, changes no result."""
+    g0 = make_grid(2, 0)  # 80 cells, 120 edges: both strides padded
+    S, vert = initial_state(g0, 12, 20.0e3, seed=5, vn_sigma=1.0, jet_u0=20.0)
+    spec = {"dt": 300.0, "nsub": 3}
+    G = D.Grid(g0, vert)
+    a = D.State(G, precision=precision)
+    b = D.State(G, precision=precision)
+    K = G.info["n_lev"]
+    nc, ne = G.info["n_cells"], G.info["n_edges"]
+    cs, es = G.info["cell_stride"], G.info["edge_stride"]
+    assert cs > nc and es > ne  # the test needs padding
+    for bufs in b.bufs:
+        for name, t in bufs.items():
+            if name == "vn":
+                v = t.view(torch.float32 if precision == "mixed" else torch.float64).view(K, es)
+                v[:, ne:] = float("nan")
+            else:
+                rows = K + 1 if name == "w" else K
+                t.view(torch.float64).view(rows, cs)[:, nc:] = float("nan")
+    a.write(S)
+    b.write(S)
+    for _ in range(3):
+        a.step(spec["dt"], spec["nsub"])
+        b.step(spec["dt"], spec["nsub"])
+    x, y = a.read(), b.read()
+    for name in FIELDS:
+        assert np.array_equal(x[name], y[name]), name
+    assert b.diag()["n_nonfinite"] == 0
+    a.close()
+    b.close()
     G.close()
