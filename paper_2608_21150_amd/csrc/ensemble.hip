@@ -428,10 +428,19 @@ dc_status dc_ensemble_autotune(dc_ensemble* E, double dt, int32_t nsub, const ch
   struct Cand {
     int threads, kb, gfac;
   };
+  // threads x the levels split into near-equal blocks (a short last level
+  // block wastes most of its wave's time), each with one block per tile and
+  // with a persistent grid of 8 blocks per compute unit
   std::vector<Cand> cands;
   for (int gf : {0, 8})
-    for (int th : {256, 128})
-      for (int kb : {1, 2, 4, 8, 16}) cands.push_back({th, kb, gf});
+    for (int th : {256, 128, 64}) {
+      int last = 0;
+      for (int nby : {1, 2, 3, 4, 5, 6, 8, 11}) {
+        const int kb = (E->K + nby - 1) / nby;
+        if (kb != last) cands.push_back({th, kb, gf});
+        last = kb;
+      }
+    }
   const Tile tile0[T_COUNT] = {E->tiles[0], E->tiles[1], E->tiles[2], E->tiles[3], E->tiles[4]};
   // per tile kind: phases that use it
   const std::vector<std::vector<int>> uses = {
@@ -469,7 +478,8 @@ dc_status dc_ensemble_autotune(dc_ensemble* E, double dt, int32_t nsub, const ch
     }
     for (int q = 0; q < 2; ++q) {
       const double v = ph[q == 0 ? K_COL_P : K_COL_C];
-      if (cands[ci].threads == 256 && cands[ci].kb == 1 && v < best_col[q]) {
+      // the column phases have no tile: only the persistent grid differs
+      if (v < best_col[q]) {
         best_col[q] = v;
         best_colg[q] = cands[ci].gfac;
       }
