@@ -70,9 +70,7 @@ struct VtStencil {
 // ---------------------------------------------------------------------------
 // edge + vertex (+ cell) pass, one launch: blocks [0, neb) are edges, the
 // next nvb blocks vertices, and in the corrector the rest cells.
-//  edges:    kinetic energy K_e = (vn^2 + vt^2)/2 with the tangential wind vt
-//            (Perot); vt itself is not stored: the edge kernel forms it again
-//            from the same vn rows it stages anyway
+//  edges:    tangential wind vt (Perot) and kinetic energy K_e = (vn^2 + vt^2)/2
 //  vertices: relative vorticity zeta_v = (1/A_v) sum sig d_e vn_e
 //  cells:    (corrector) the divergence-damping field D2 = laps(D) from
 //            D = div vn*, which the predictor's column kernel stored.
@@ -84,6 +82,7 @@ struct BVc {
   struct Args {
     const R* vn;
     R* zeta;
+    R* vt;
     R* ke;
     R* d2;
     const R* dv;  // corrector: D = div vn*
@@ -104,6 +103,7 @@ struct BVc {
       const int base = bx * blockDim.x;
       const int e = base + threadIdx.x;
       const bool in = e < g.ne;
+      R* __restrict__ vt = args.vt;
       R* __restrict__ ke = args.ke;
       VtStencil<R> vts;
       if (in) vts.load(g, e);
@@ -121,7 +121,9 @@ struct BVc {
             x = (unsigned)l < (unsigned)blockDim.x ? x : row[vts.idx[q]];
             b += vts.w[1 + q] * x;
           }
-          ke[(size_t)k * g.es + e] = R(0.5) * (a * a + b * b);
+          const size_t r = (size_t)k * g.es + e;
+          vt[r] = b;
+          ke[r] = R(0.5) * (a * a + b * b);
         }
       }
       __syncthreads();  // the next tile of a persistent block reuses s_row
@@ -184,6 +186,7 @@ struct BEdge {
     const R* vn;
     const R* zeta;
     const R* ke;  // K_e of this pass's vn
+    const R* vt;  // vt of this pass's vn
     const double* w;
     const double* ex;
     const double* th;
@@ -201,6 +204,7 @@ struct BEdge {
     R* __restrict__ gw = args.gw;
     const R* __restrict__ zeta = args.zeta;
     const R* __restrict__ ke = args.ke;
+    const R* __restrict__ vtf = args.vt;
     const double* __restrict__ w = args.w;
     const double* __restrict__ ex = args.ex;
     const double* __restrict__ th = args.th;
@@ -216,7 +220,6 @@ struct BEdge {
     const bool in = base + (int)threadIdx.x < g.ne;
     const int e = in ? base + (int)threadIdx.x : 0;
     __shared__ R s_ke[2][kThreads];
-    __shared__ R s_vn[2][kThreads];
     const int K = g.K;
     const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
     const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
@@ -229,10 +232,6 @@ struct BEdge {
     int rh[4];
   #pragma unroll
     for (int s = 0; s < 4; ++s) rh[s] = g.e2c2e[s * g.es + e];
-    // Perot weights of vt: the edge itself, then the same four edges
-    R kw[5];
-  #pragma unroll
-    for (int s = 0; s < 5; ++s) kw[s] = (R)g.kvt[s * g.es + e];
     const R third = R(1) / R(3);
     const double* idzf = vt_row(g, VT_IDZF);
     const double* exref = vt_row(g, VT_EXREF);
@@ -252,28 +251,22 @@ struct BEdge {
       const R ze = R(0.5) * (zr[v0] + zr[v1]);
       // K_e of the rhombus edges: from the block's row in LDS where they lie
       // in the block, else from memory
-      // and vn of the same edges for vt (Perot), both staged the same way
       const R* kr = ke + (size_t)j * g.es;
-      const R* vr = vn + (size_t)j * g.es;
       s_ke[j & 1][threadIdx.x] = kr[e];
-      s_vn[j & 1][threadIdx.x] = vj;
       __syncthreads();
       R kq[4];
-      R vt = kw[0] * vj;
   #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int l = rh[q] - base;
-        const bool inb = (unsigned)l < (unsigned)blockDim.x;
         const R x = s_ke[j & 1][l & (kThreads - 1)];
-        const R y = s_vn[j & 1][l & (kThreads - 1)];
-        kq[q] = inb ? x : kr[rh[q]];
-        vt += kw[1 + q] * (inb ? y : vr[rh[q]]);
+        kq[q] = (unsigned)l < (unsigned)blockDim.x ? x : kr[rh[q]];
       }
       const R kgrad = ((kq[2] + kq[3]) - (kq[0] + kq[1])) * third * invd_r;
       const R wef = (R)(0.5 * (0.5 * (wa0 + wa1) + 0.5 * (wb0 + wb1)));
       // this edge's share of the horizontal advection of w at half level j:
       // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
       if (j > 0 && in) gw[re] = le * ie_top * (R)(wa1 - wa0);
+      const R vt = vtf[re];
       const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
       const size_t rc = (size_t)j * g.cs;
       const double exr = exref[j];
@@ -1198,11 +1191,11 @@ SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& 
   int lm;
   const int P = col_chunks_lm(g.K, &lm);
   const int neb = cdiv(g.ne, T[T_VC].threads), nvb = cdiv(g.nv, T[T_VC].threads);
-  s.vc_p = {b.vn, b.zeta, b.kc, nullptr, nullptr, neb, nvb, T[T_VC].kb};
-  s.e_p = {b.vn, b.zeta, b.kc, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
+  s.vc_p = {b.vn, b.zeta, b.vt, b.kc, nullptr, nullptr, neb, nvb, T[T_VC].kb};
+  s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
   s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr}, c, P};
-  s.vc_c = {b.vns, b.zeta, b.kc, b.d2, b.dvn, neb, nvb, T[T_VC].kb};
-  s.e_c = {b.vns, b.zeta, b.kc, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
+  s.vc_c = {b.vns, b.zeta, b.vt, b.kc, b.d2, b.dvn, neb, nvb, T[T_VC].kb};
+  s.e_c = {b.vns, b.zeta, b.kc, b.vt, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
   s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, P};
   return s;
 }
