@@ -174,9 +174,9 @@ struct BVc {
 
 // ---------------------------------------------------------------------------
 // edge: advective tendency T_vn and the horizontal momentum update.
-//  predictor: vn* = vn + dtau (T_vn - cpd theta_e grad pi')       -> tvn0, vns
-//  corrector: vn' = vn_now + dtau (a0 T0 + a1 T* - cpd theta_e grad pi')
-//                   - c4 Abar^2 grad(D2)                             -> vn_out
+//  predictor: vn* = vn + dtau (T_vn - cpd theta_e grad pi')       -> vns, and
+//             X = a0 T_vn - cpd theta_e grad pi' stored in tvn0
+//  corrector: vn' = vn_now + dtau (X + a1 T*) - c4 Abar^2 grad(D2)  -> vn_out
 // The pressure-gradient term is formed from the state at the start of the
 // substep in both passes.
 // ---------------------------------------------------------------------------
@@ -269,18 +269,22 @@ struct BEdge {
       const R vt = vtf[re];
       const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
       const size_t rc = (size_t)j * g.cs;
-      const double exr = exref[j];
-      const R gex = (R)((ex[rc + c1] - exr) - (ex[rc + c0] - exr)) * invd_r;
-      const R the = (R)(0.5 * (th[rc + c0] + th[rc + c1]));
-      const R pgf = (R)cf.cpd * the * gex;
       if (!CORR) {
+        // the pressure-gradient term comes from the substep's start state in
+        // both passes: the predictor forms it once and stores it with its
+        // share of the tendency, a0 T_vn0 - cpd theta_e grad pi', which is all
+        // the corrector needs of either
+        const double exr = exref[j];
+        const R gex = (R)((ex[rc + c1] - exr) - (ex[rc + c0] - exr)) * invd_r;
+        const R the = (R)(0.5 * (th[rc + c0] + th[rc + c1]));
+        const R pgf = (R)cf.cpd * the * gex;
         if (in) {
-          tvn0[re] = tvn;
+          tvn0[re] = (R)cf.a0 * tvn - pgf;
           vout[re] = vj + (R)cf.dtau * (tvn - pgf);
         }
       } else {
         const R dd = (d2[rc + c1] - d2[rc + c0]) * invd_r;
-        if (in) vout[re] = vn_now[re] + (R)cf.dtau * ((R)cf.a0 * tvn0[re] + (R)cf.a1 * tvn - pgf) - (R)cf.c4a2 * dd;
+        if (in) vout[re] = vn_now[re] + (R)cf.dtau * (tvn0[re] + (R)cf.a1 * tvn) - (R)cf.c4a2 * dd;
       }
       vup = vj;
       vj = vdn;
