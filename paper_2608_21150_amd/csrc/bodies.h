@@ -373,7 +373,9 @@ struct ColPhaseArgs {
 template <typename R, bool CORR, int LM>
 struct BCol {
   using Args = ColPhaseArgs<R>;
-  static constexpr int kThreads = 512;
+  // the predictor runs up to 12 waves per block, the corrector up to 8 (its
+  // registers allow two waves per SIMD only)
+  static constexpr int kThreads = CORR ? 512 : 768;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const ColArgs<R>& a = args.a;
     body(g, args.cf, args.P, bx, g.vert, g.tau, a.w, a.rho, a.ex, a.th, a.gw, a.vnf, a.tw0, a.dv_out, a.ws, a.w_out,
@@ -1132,12 +1134,18 @@ struct Geom {
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// Column chunking: at most 8 waves (chunks) per block of 64 columns, chunk
-// length LM in {8, 12, 16} (the smallest that fits); chunks hold >= 2 rows
-// whenever there is more than one.  Supports n_lev <= 129.
-inline int col_chunks_lm(int K, int* lm) {
+// Column chunking: chunk length LM in {8, 12, 16}, chunks hold >= 2 rows
+// whenever there is more than one; supports n_lev <= 129.  The corrector (at
+// most 8 waves per block: its registers allow two waves per SIMD) takes the
+// smallest LM that fits in 8 chunks.  The predictor, at three waves per SIMD,
+// takes up to 12 chunks: 8-row chunks up to 96 rows, 12-row chunks beyond,
+// so deep columns get more waves and shorter serial sweeps.
+inline int col_chunks_lm(int K, bool corr, int* lm) {
   const int nrow = std::max(K - 1, 0);
-  *lm = nrow <= 64 ? 8 : (nrow <= 96 ? 12 : 16);
+  if (corr)
+    *lm = nrow <= 64 ? 8 : (nrow <= 96 ? 12 : 16);
+  else
+    *lm = nrow <= 96 ? 8 : 12;
   return std::max(1, (nrow + *lm - 1) / *lm);
 }
 
@@ -1157,7 +1165,7 @@ inline Geom geom_of(int phase, const DevGrid& g, const Tile* T) {
     }
     case K_COL_P:
     case K_COL_C: {
-      const int P = col_chunks_lm(g.K, &lm);
+      const int P = col_chunks_lm(g.K, phase == K_COL_C, &lm);
       return {cdiv(g.nc, 64), 1, 64 * P, P > 1 ? 6 * sizeof(double) * 64 * (size_t)P : 0};
     }
     case K_DVERT: {
@@ -1193,14 +1201,14 @@ template <typename R>
 SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* T) {
   SubstepArgs<R> s;
   int lm;
-  const int P = col_chunks_lm(g.K, &lm);
+  const int Pp = col_chunks_lm(g.K, false, &lm), Pc = col_chunks_lm(g.K, true, &lm);
   const int neb = cdiv(g.ne, T[T_VC].threads), nvb = cdiv(g.nv, T[T_VC].threads);
   s.vc_p = {b.vn, b.zeta, b.vt, b.kc, nullptr, nullptr, neb, nvb, T[T_VC].kb};
   s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
-  s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr}, c, P};
+  s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr}, c, Pp};
   s.vc_c = {b.vns, b.zeta, b.vt, b.kc, b.d2, b.dvn, neb, nvb, T[T_VC].kb};
   s.e_c = {b.vns, b.zeta, b.kc, b.vt, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
-  s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, P};
+  s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, Pc};
   return s;
 }
 

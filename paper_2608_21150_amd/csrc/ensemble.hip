@@ -115,7 +115,7 @@ void plan_step(dc_ensemble* E, double dt, int nsub, int parity, std::vector<char
     }
     Rec r{};
     r.phase = phase;
-    col_chunks_lm(E->K, &r.lm);
+    col_chunks_lm(E->K, phase == K_COL_C, &r.lm);
     r.jobs_off = append_table(blob, jobs, ts, &r.ts_off);
     r.nm = nm;
     r.total = ts[nm];

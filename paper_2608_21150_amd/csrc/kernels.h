@@ -118,8 +118,6 @@ template <typename R>
 void launch_diag(const DevGrid& g, const R* vn, const double* w, const double* rho, const double* th,
                  const double* ex, double* partial, double* out, hipStream_t s);
 int diag_partial_count(const DevGrid& g);
-// chunks (waves) per 64-column block of the column kernel; *lm = rows per chunk
-int col_chunks(int K, int* lm);
 
 // indices into the tile table
 enum TileId { T_VC = 0, T_EDGE, T_DVERT, T_DCELL, T_DEDGE, T_COUNT };

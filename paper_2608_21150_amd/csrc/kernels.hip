@@ -127,7 +127,6 @@ const char* const kKernelNames[K_COUNT] = {
     "vort_ke_corr", "edge_corr", "column_corr",
     "diff_vertex", "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2"};
 
-int col_chunks(int K, int* lm) { return bodies::col_chunks_lm(K, lm); }
 
 int diag_partial_count(const DevGrid& g) {
   return (g.nc + kDiagThreads - 1) / kDiagThreads + (g.ne + kDiagThreads - 1) / kDiagThreads;
@@ -147,7 +146,7 @@ void one(int id, const DevGrid& g, const typename B::Args& a, const Tile* T, hip
 template <typename R, bool CORR>
 void one_col(int id, const DevGrid& g, const bodies::ColPhaseArgs<R>& a, const Tile* T, hipStream_t s, Prof* prof) {
   int lm;
-  bodies::col_chunks_lm(g.K, &lm);
+  bodies::col_chunks_lm(g.K, CORR, &lm);
   if (lm == 8)
     one<bodies::BCol<R, CORR, 8>>(id, g, a, T, s, prof);
   else if (lm == 12)
