@@ -97,10 +97,12 @@ def test_small_and_ragged_grids(name):
 
 @pytest.mark.parametrize("n_lev", [66, 90, 98, 129])
 def test_deep_columns_every_chunk_length(n_lev):
-    """The column solver splits the K-1 interior rows into chunks of 8, 12 or
-    16 rows by depth: K = 66 and 90 use 12-row chunks (90 is the R2B8
-    workload's depth), K = 98 and 129 (the maximum) 16-row chunks.  Jet,
-    bumps and noise on R2B1, model top 75 km, two steps of 3 substeps."""
+    """The column solver splits the K-1 interior rows into chunks by depth:
+    the corrector into at most 8 chunks of 8, 12 or 16 rows (K = 66 and 90:
+    12 rows, 90 being the R2B8 workload's depth; K = 98 and 129, the maximum:
+    16 rows), the predictor into at most 12 chunks of 8 rows up to K = 97
+    (K = 90: 12 chunks) and of 12 rows beyond.  Jet, bumps and noise on R2B1,
+    model top 75 km, two steps of 3 substeps."""
     g0 = make_grid(2, 1)
     S, vert = initial_state(g0, n_lev, 75.0e3, seed=21, vn_sigma=1.0, jet_u0=35.0, n_bumps=4,
                             bump_radius=2000.0e3)
