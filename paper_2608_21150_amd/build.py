@@ -65,7 +65,23 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *[o for _, o in jobs], "-o", tmp])
     os.replace(tmp, LIB)
+    build_c_driver()
     return LIB
+
+
+def build_c_driver() -> str:
+    """The plain-C host driver (examples/c_driver.c): links the library and
+    the system HIP runtime, finds libdycore.so next to the package."""
+    src = os.path.join(PKG, "examples", "c_driver.c")
+    out = os.path.join(PKG, "examples", "c_driver")
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cc = shutil.which("gcc") or "gcc"
+    tmp = out + ".tmp"
+    _run([cc, "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I", os.path.join(rocm, "include"),
+          src, "-o", tmp, "-L", PKG, "-ldycore", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+          "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib")])
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

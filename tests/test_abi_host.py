@@ -31,6 +31,17 @@ def test_every_declared_symbol_is_exported():
         assert hasattr(lib, n), n
 
 
+def test_c_driver_is_built_and_checks_its_arguments():
+    """The plain-C host driver links the library; without arguments it prints
+    its usage and touches no GPU."""
+    import subprocess
+
+    drv = os.path.join(ROOT, "paper_2608_21150_amd", "examples", "c_driver")
+    assert os.access(drv, os.X_OK), "build() builds the C driver"
+    r = subprocess.run([drv], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage: c_driver IN OUT" in r.stderr
+
+
 @pytest.mark.parametrize("n,k,sfc", [(1, 0, False), (2, 0, False), (2, 1, True), (2, 2, False), (2, 3, True)])
 def test_tables_bit_exact(grids, n, k, sfc):
     g = grids(n, k)
