@@ -27,5 +27,6 @@ def default_params():
         "smag_cap": 16.0,       # nu <= A_e / (smag_cap * dt)
         "hdiff_k4": 1.0 / 128.0,  # 4th-order background diffusion, k4 * A_e^2
         "diffuse_w": 1,         # apply 2nd-order Smagorinsky diffusion to w
+        "diffuse_theta": 0,     # optional 2nd-order Smagorinsky diffusion of theta_v, exner updated
         "rd": RD, "cpd": CPD, "cvd": CVD, "omega": OMEGA,
     }

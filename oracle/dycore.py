@@ -275,6 +275,16 @@ def diffusion(g, p, S, dt, wts=None):
     out = dict(S)
     out["vn"] = vn_new
     out["w"] = w_new
+    if p.get("diffuse_theta", 0):
+        # Section 4.1: diffusion optionally acts on temperature and Exner too.
+        # Reading: theta_v takes the same second-order Smagorinsky form as w,
+        # at full levels with nu averaged over the cell's edges; Exner follows
+        # the equation of state linearised at fixed rho, dpi/pi = (R_d/c_vd)
+        # dtheta_v/theta_v, so that pressure changes only at second order.
+        nu_f = op.avg_c(g, nu)
+        dth = dt * nu_f * op.laps(g, S["theta_v"])
+        out["theta_v"] = S["theta_v"] + dth
+        out["exner"] = S["exner"] * (1.0 + p["rd"] / p["cvd"] * dth / S["theta_v"])
     return out
 
 

@@ -184,3 +184,44 @@ def test_equation_of_state_round_trip():
     from synth.state import _surface_pressure_jet
     r = _surface_pressure_jet(np.array([0.0]), 35.0, 6.371e6)[0] / _surface_pressure_jet(np.array([np.pi / 2]), 35.0, 6.371e6)[0]
     assert abs(r - 1.168) < 1e-3
+
+
+def _theta_diffusion(g, S, dt=600.0):
+    p = default_params()
+    p["diffuse_theta"] = 1
+    out = dycore.diffusion(g, p, S, dt)
+    return p, out
+
+
+def test_theta_diffusion_leaves_uniform_levels_alone(r2b3):
+    """A theta_v that is constant on every level has no horizontal Laplacian:
+    theta_v and exner come out bitwise unchanged however large nu is."""
+    S, vert = initial_state(r2b3, 4, 10e3, seed=3, vn_sigma=20.0)
+    g = Grid(r2b3, vert)
+    _, out = _theta_diffusion(g, S)
+    assert np.all(np.ptp(S["theta_v"], axis=1) == 0.0)  # the generator's reference column
+    assert np.array_equal(out["theta_v"], S["theta_v"])
+    assert np.array_equal(out["exner"], S["exner"])
+
+
+def test_theta_diffusion_maximum_principle_and_pressure(r2b3):
+    """theta_v bumps: a cell hotter than its three neighbours cools and a
+    colder one warms (nu >= 0, positive Laplacian weights); exner moves with
+    theta_v as the equation of state at fixed rho says, pi ~ (rho theta_v)^(R_d/c_vd),
+    to second order in the increment."""
+    S, vert = initial_state(r2b3, 4, 10e3, seed=4, vn_sigma=20.0, t_sigma=1.0)
+    g = Grid(r2b3, vert)
+    p, out = _theta_diffusion(g, S)
+    th, dth = S["theta_v"], out["theta_v"] - S["theta_v"]
+    nb = th[:, g.c2e2c]  # [K][C][3]
+    hot = np.all(th[:, :, None] > nb, axis=2)
+    cold = np.all(th[:, :, None] < nb, axis=2)
+    assert hot.sum() > 10 and cold.sum() > 10
+    assert np.all(dth[hot] <= 0.0) and np.any(dth[hot] < 0.0)
+    assert np.all(dth[cold] >= 0.0) and np.any(dth[cold] > 0.0)
+    a = p["rd"] / p["cvd"]
+    x = dth / th
+    assert np.max(np.abs(x)) > 1e-6
+    resid = out["exner"] / S["exner"] - (1.0 + x) ** a
+    assert np.max(np.abs(resid)) <= 0.2 * np.max(x * x) + 1e-15
+    assert np.array_equal(out["rho"], S["rho"])
