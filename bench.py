@@ -378,6 +378,7 @@ def main():
     ap.add_argument("--eval-steps", type=int, default=500, help="surrogate: steps of every evaluation run")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch tiles")
+    ap.add_argument("--no-theta", action="store_true", help="skip the run with the theta_v diffusion on")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -423,12 +424,12 @@ def main():
     torch.cuda.set_device(dev)
     G = D.Grid(g0, vert, sfc=sfc)
 
-    def run(precision, steps, warmup, tune):
+    def run(precision, steps, warmup, tune, params=None):
         """Tune (outside every timed region), warm up, then two passes of
         `steps` steps: the first records events around every launch (the
         per-kernel table), the second is the timed one and records events
         around the launches of the dominant kernel only."""
-        st = D.State(G, precision=precision, device=dev)
+        st = D.State(G, precision=precision, device=dev, params=params)
         st.write(S)
         tune_s = None
         if tune:
@@ -518,6 +519,13 @@ def main():
                          "mass_rel_diff_vs_fp64": d2["mass"] / diag["mass"] - 1.0,
                          "tiles": {k: f"{t}x{l}" for k, (t, l) in R2["tiles"].items()},
                          "kernels": {n: round(1e3 * t / c, 2) for n, (c, t) in R2["prof"].items() if c}}
+    if not args.no_theta:
+        # the optional theta_v/exner diffusion, same timing: what it adds to a step
+        print("[bench] theta_v diffusion run", file=sys.stderr, flush=True)
+        R3 = run(args.precision, args.steps, args.warmup, tune, params=D.default_params(diffuse_theta=1))
+        line["theta_diffusion"] = {"ms_per_step": R3["ms"] / args.steps, "cost_vs_plain": R3["ms"] / ms,
+                                   "diff_cell_vertex2_us": round(1e3 * R3["prof"]["diff_cell_vertex2"][1]
+                                                                 / R3["prof"]["diff_cell_vertex2"][0], 2)}
     G.close()
     if not args.no_cpu_baseline:
         print("[bench] oracle on the host", file=sys.stderr, flush=True)

@@ -128,6 +128,10 @@ typedef struct {
   double omega;          /* planetary angular velocity [1/s]                              */
   int32_t diffuse_w;     /* 1: diffuse w with the Smagorinsky viscosity                   */
   int32_t check_finite;  /* 1: dc_dycore_step checks the state and returns DC_ENONFINITE  */
+  int32_t diffuse_theta; /* 1: the diffusion step also diffuses theta_v (Smagorinsky, as w,
+                            at full levels with nu averaged over the cell's edges) and
+                            moves exner with it, dpi/pi = (R_d/c_vd) dtheta_v/theta_v
+                            (the equation of state at fixed rho); plain diffusion only */
 } dc_params;
 
 /* Device pointers of the five prognostic fields, [level][entity] padded.

@@ -46,7 +46,7 @@ dc_status fail(dc_status code, const std::string& msg) {
 size_t elem_size(dc_precision prec) { return prec == DC_PREC_MIXED ? sizeof(float) : sizeof(double); }
 
 struct Layout {
-  size_t vt, tvn0, vns, kc, d2, zeta, vv, gw, dvn, wstar, wtmp, tw0, fe, tau, dpart, dout;
+  size_t vt, tvn0, vns, kc, d2, zeta, vv, gw, dvn, wstar, wtmp, ttmp, tw0, fe, tau, dpart, dout;
   size_t s_tmlp, s_cl, s_fj, s_fr, s_cnt;  // surrogate mode only
   size_t total;
 };
@@ -72,6 +72,7 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff)
   L.dvn = take(K * h.cs * r);
   L.wstar = take(K1 * h.cs * 8);
   L.wtmp = take(K1 * h.cs * 8);
+  L.ttmp = take(K * h.cs * 8);  // theta_v staged for its diffusion
   L.tw0 = take(K1 * h.cs * 8);
   L.fe = take(h.es * 8);
   L.tau = take(K1 * 8);
@@ -170,6 +171,13 @@ void* field_ptr(const dc_fields& f, int field) {
   }
 }
 
+// the theta_v diffusion's fields: theta_v staged by the last substep, the
+// current buffer set's theta_v and exner (null when it is off)
+ThetaDiff theta_diff(const dc_state* s, const dc_fields& cur) {
+  if (!s->p.diffuse_theta) return ThetaDiff{nullptr, nullptr, nullptr};
+  return ThetaDiff{s->ttmp, static_cast<double*>(cur.theta_v), static_cast<double*>(cur.exner)};
+}
+
 template <typename R>
 void enqueue_step(dc_state* s, double dt, int nsub) {
   const StepCoef c = make_coef(s, dt, nsub);
@@ -181,7 +189,8 @@ void enqueue_step(dc_state* s, double dt, int nsub) {
     const dc_fields& cur = s->buf[s->cur];
     launch_diffusion<R>(s->d, static_cast<R*>(cur.vn), s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt),
                         static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
-                        static_cast<R*>(s->zeta), static_cast<R*>(s->vv), c, s->tiles, s->stream, &s->prof);
+                        static_cast<R*>(s->zeta), static_cast<R*>(s->vv), theta_diff(s, cur), c, s->tiles, s->stream,
+                        &s->prof);
   }
 }
 
@@ -196,7 +205,8 @@ void enqueue_trial_step(dc_state* s, double dt, int nsub) {
     const dc_fields& cur = s->buf[s->cur];
     launch_diffusion<R>(s->d, static_cast<R*>(cur.vn), s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt),
                         static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
-                        static_cast<R*>(s->zeta), static_cast<R*>(s->vv), c, s->tiles, s->stream, &s->prof);
+                        static_cast<R*>(s->zeta), static_cast<R*>(s->vv), theta_diff(s, cur), c, s->tiles, s->stream,
+                        &s->prof);
   }
 }
 
@@ -251,6 +261,7 @@ dc_status dc_params_default(dc_params* p) {
   p->omega = 7.29212e-5;
   p->diffuse_w = 1;
   p->check_finite = 0;
+  p->diffuse_theta = 0;
   return DC_OK;
 }
 
@@ -356,8 +367,10 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   const dc_params& p = *params;
   if (!(p.eta >= 0.5 && p.eta <= 1.0) || !(p.rd > 0 && p.cpd > p.rd && p.cvd > 0) || !(p.smag_cap > 0) ||
       !(p.rayleigh_zfrac > 0 && p.rayleigh_zfrac < 1) || p.rayleigh_tau0 < 0 || p.divdamp_c4 < 0 || p.hdiff_k4 < 0 ||
-      p.smag_cs < 0 || !std::isfinite(p.omega))
+      p.smag_cs < 0 || !std::isfinite(p.omega) || (p.diffuse_theta != 0 && p.diffuse_theta != 1))
     return fail(DC_EINVAL, "parameter out of range");
+  if (p.diffuse_theta && diff == DC_DIFF_SURROGATE)
+    return fail(DC_EINVAL, "theta_v diffusion is available with the plain diffusion only");
   dc_status st = ensure_uploaded(g);
   if (st != DC_OK) return st;
   int dev = -1;
@@ -387,6 +400,7 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->dvn = w + L.dvn;
   s->wstar = reinterpret_cast<double*>(w + L.wstar);
   s->wtmp = reinterpret_cast<double*>(w + L.wtmp);
+  s->ttmp = reinterpret_cast<double*>(w + L.ttmp);
   s->tw0 = reinterpret_cast<double*>(w + L.tw0);
   s->fe = reinterpret_cast<double*>(w + L.fe);
   s->tau = reinterpret_cast<double*>(w + L.tau);

@@ -993,6 +993,9 @@ struct BDcv2 {
     double* w_out;
     R* divl1;
     R* curll1;
+    const double* th_in;  // theta_v diffusion (cf.diffuse_theta): theta_v in,
+    double* th_out;       // theta_v out,
+    double* ex;           // exner, updated in place
     int ncb;
     StepCoef cf;
     int kb;
@@ -1027,13 +1030,27 @@ struct BDcv2 {
       }
       for (int k = k0; k < k1; ++k) {
         R nuk[3] = {R(0), R(0), R(0)};
+        const size_t r = (size_t)k * g.cs + c;
         if (k < K) {
           const R* row = l1 + (size_t)k * g.es;
-          divl1[(size_t)k * g.cs + c] = dq.apply(row);
+          divl1[r] = dq.apply(row);
   #pragma unroll
           for (int i = 0; i < 3; ++i) nuk[i] = nu[(size_t)k * g.es + ie[i]];
+          if (cf.diffuse_theta) {
+            // theta_v at full level k: the Smagorinsky form of w with nu
+            // averaged over the cell's edges; exner by the equation of state
+            // at fixed rho, dpi/pi = (R_d/c_vd) dtheta_v/theta_v
+            const double* tr = args.th_in + (size_t)k * g.cs;
+            const double tc = tr[c];
+            const R nuf = (nuk[0] + nuk[1] + nuk[2]) / R(3);
+            double lt = 0.0;
+  #pragma unroll
+            for (int i = 0; i < 3; ++i) lt += lq.kl[i] * (tr[lq.nb[i]] - tc);
+            const double dth = cf.dt * (double)nuf * lt;
+            args.th_out[r] = tc + dth;
+            args.ex[r] = args.ex[r] * (1.0 + cf.rd_cvd * dth / tc);
+          }
         }
-        const size_t r = (size_t)k * g.cs + c;
         w_out[r] = dif_w<R>(g, lq, w_in, nup, nuk, c, k, cf);
   #pragma unroll
         for (int i = 0; i < 3; ++i) nup[i] = nuk[i];
@@ -1225,12 +1242,14 @@ struct DiffusionArgs {
 // zeta, vv are workspace fields (edge, edge, cell, cell, vertex, 3 x vertex)
 template <typename R>
 DiffusionArgs<R> diffusion_args(const DevGrid& g, R* vn, const double* w_in, double* w_out, R* l1, R* nu, R* dv,
-                                R* dl1, R* zeta, R* vv, const StepCoef& c, const Tile* T) {
+                                R* dl1, R* zeta, R* vv, const StepCoef& c, const Tile* T,
+                                const ThetaDiff& td = ThetaDiff{nullptr, nullptr, nullptr}) {
   DiffusionArgs<R> d;
   d.dv = {vn, vv, zeta, T[T_DVERT].kb};
   d.dd = {vn, dv, T[T_DCELL].kb};
   d.d1 = {dv, zeta, vv, l1, nu, c, T[T_DEDGE].kb};
-  d.cv = {l1, nu, w_in, w_out, dl1, zeta, cdiv(g.nc, T[T_DCELL].threads), c, T[T_DCELL].kb};
+  d.cv = {l1, nu, w_in, w_out, dl1, zeta, td.th_in, td.th_out, td.ex, cdiv(g.nc, T[T_DCELL].threads), c,
+          T[T_DCELL].kb};
   d.d2 = {vn, l1, nu, dl1, zeta, c, T[T_DEDGE].kb};
   return d;
 }

@@ -146,7 +146,10 @@ void plan_step(dc_ensemble* E, double dt, int nsub, int parity, std::vector<char
       da[k] = diffusion_args<R>(s->d, static_cast<R*>(f.vn), s->wtmp, static_cast<double*>(f.w),
                                 static_cast<R*>(s->vt), static_cast<R*>(s->tvn0), static_cast<R*>(s->kc),
                                 static_cast<R*>(s->d2), static_cast<R*>(s->zeta), static_cast<R*>(s->vv),
-                                make_coef(s, dt, nsub), E->tiles);
+                                make_coef(s, dt, nsub), E->tiles,
+                                s->p.diffuse_theta ? ThetaDiff{s->ttmp, static_cast<double*>(f.theta_v),
+                                                               static_cast<double*>(f.exner)}
+                                                   : ThetaDiff{nullptr, nullptr, nullptr});
     }
     table(K_DVERT, [&](int k) { return da[k].dv; });
     table(K_DDIV, [&](int k) { return da[k].dd; });

@@ -75,7 +75,7 @@ struct Tile {
 
 struct StepCoef {
   double dtau, dt, eta, a0, a1, cpd, rd_cvd, cvd_rd, c4a2, cs, cap, k4;
-  int diffuse_w;
+  int diffuse_w, diffuse_theta;
 };
 
 // Pointers of one predictor/corrector/diffusion pass; the meaning of each
@@ -99,10 +99,17 @@ struct Bufs {
 template <typename R>
 void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* tiles, hipStream_t s,
                     Prof* prof);
+// theta_v diffusion (optional): theta_v read from th_in, written to th_out,
+// exner updated in place; all null when it is off
+struct ThetaDiff {
+  const double* th_in;
+  double* th_out;
+  double* ex;
+};
 template <typename R>
 void launch_diffusion(const DevGrid& g, R* vn, const double* w_in, double* w_out, R* vt_l1, R* nu, R* kc_div,
-                      R* d2_divl1, R* zeta, R* vv, const StepCoef& c, const Tile* tiles, hipStream_t s,
-                      Prof* prof);
+                      R* d2_divl1, R* zeta, R* vv, const ThetaDiff& td, const StepCoef& c, const Tile* tiles,
+                      hipStream_t s, Prof* prof);
 // The diffusion in two parts: the front (vertex vectors and vorticity, div vn,
 // L1 and the viscosity, div L1 and curl L1, the w diffusion) and the back
 // (L2 and the vn update).  curll1 may differ from zeta so that the vorticity

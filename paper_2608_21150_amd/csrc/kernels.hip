@@ -173,9 +173,10 @@ void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const
 
 template <typename R>
 void launch_diffusion(const DevGrid& g, R* vn, const double* w_in, double* w_out, R* l1, R* nu, R* dv, R* dl1,
-                      R* zeta, R* vv, const StepCoef& c, const Tile* T, hipStream_t s, Prof* prof) {
+                      R* zeta, R* vv, const ThetaDiff& td, const StepCoef& c, const Tile* T, hipStream_t s,
+                      Prof* prof) {
   using namespace bodies;
-  const DiffusionArgs<R> d = diffusion_args<R>(g, vn, w_in, w_out, l1, nu, dv, dl1, zeta, vv, c, T);
+  const DiffusionArgs<R> d = diffusion_args<R>(g, vn, w_in, w_out, l1, nu, dv, dl1, zeta, vv, c, T, td);
   one<BDvert<R>>(K_DVERT, g, d.dv, T, s, prof);
   one<BDiv<R>>(K_DDIV, g, d.dd, T, s, prof);
   one<BDedge1<R>>(K_DEDGE1, g, d.d1, T, s, prof);
@@ -218,9 +219,11 @@ template void launch_substep<double>(const DevGrid&, const Bufs<double>&, const 
 template void launch_substep<float>(const DevGrid&, const Bufs<float>&, const StepCoef&, const Tile*, hipStream_t,
                                     Prof*);
 template void launch_diffusion<double>(const DevGrid&, double*, const double*, double*, double*, double*, double*,
-                                       double*, double*, double*, const StepCoef&, const Tile*, hipStream_t, Prof*);
+                                       double*, double*, double*, const ThetaDiff&, const StepCoef&, const Tile*,
+                                       hipStream_t, Prof*);
 template void launch_diffusion<float>(const DevGrid&, float*, const double*, double*, float*, float*, float*, float*,
-                                      float*, float*, const StepCoef&, const Tile*, hipStream_t, Prof*);
+                                      float*, float*, const ThetaDiff&, const StepCoef&, const Tile*, hipStream_t,
+                                      Prof*);
 template void launch_diffusion_front<double>(const DevGrid&, const double*, const double*, double*, double*,
                                              double*, double*, double*, double*, double*, double*, const StepCoef&,
                                              const Tile*, hipStream_t, Prof*);

@@ -46,7 +46,7 @@ struct dc_state {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv, *gw, *dvn;
-  double *wstar, *wtmp, *tw0, *fe, *tau, *diag_part, *diag_out;
+  double *wstar, *wtmp, *ttmp, *tw0, *fe, *tau, *diag_part, *diag_out;
   // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
   // curl L1 of the diffusion front [K][vs], judge and range flags [es],
   // counters (4 int, then one 64-bit)
@@ -77,6 +77,7 @@ inline StepCoef make_coef(const dc_state* s, double dt, int nsub) {
   c.cap = s->p.smag_cap;
   c.k4 = s->p.hdiff_k4;
   c.diffuse_w = s->p.diffuse_w;
+  c.diffuse_theta = s->p.diffuse_theta;
   return c;
 }
 
@@ -108,7 +109,8 @@ Bufs<R> substep_bufs(const dc_state* s, int cur_idx, bool w_to_staging) {
   b.w_out = w_to_staging ? s->wtmp : static_cast<double*>(nxt.w);
   b.rho_out = static_cast<double*>(nxt.rho);
   b.ex_out = static_cast<double*>(nxt.exner);
-  b.th_out = static_cast<double*>(nxt.theta_v);
+  // theta_v goes to its staging field too when the diffusion diffuses it
+  b.th_out = w_to_staging && s->p.diffuse_theta ? s->ttmp : static_cast<double*>(nxt.theta_v);
   return b;
 }
 

@@ -204,3 +204,48 @@ def test_mixed_precision_error_vs_fp64():
     for k in ("vn", "rho", "exner", "theta_v"):
         assert errs[k] <= 1e-4, (k, errs[k])
     assert abs(db["mass"] / da["mass"] - 1) < 1e-12
+
+
+def test_theta_diffusion_parity_and_batching():
+    """The optional theta_v/exner diffusion: FP64 against the oracle with the
+    same option after 10 steps, the option changes theta_v, mixed precision
+    stays close to FP64, an ensemble member equals its solo run bit for bit,
+    and the surrogate mode refuses it."""
+    g0, S, vert, spec = build_workload("r2b2_k30")
+    p_on = D.default_params(diffuse_theta=1)
+    out, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"], params=p_on)
+    og = OGrid(g0, vert)
+    wts = O.vertex_lsq_weights(og)
+    po = default_params()
+    po["diffuse_theta"] = 1
+    ref = S
+    for _ in range(spec["steps"]):
+        ref = O.step(og, ref, spec["dt"], spec["nsub"], po, diffuse=True, wts=wts)
+    errs = {k: rel_l2(out[k], ref[k]) for k in FIELDS}
+    print("theta diffusion, rel L2 vs oracle:", errs)
+    for k in FIELDS:
+        assert errs[k] <= 1e-11, (k, errs[k])
+    off, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"])
+    assert rel_l2(out["theta_v"], off["theta_v"]) > 1e-9
+    mixed, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"], precision="mixed", params=p_on)
+    for k in ("vn", "rho", "exner", "theta_v"):
+        assert rel_l2(mixed[k], out[k]) <= 1e-4, k
+    G = D.Grid(g0, vert)
+    a = D.State(G, params=p_on)
+    b = D.State(G, params=p_on)
+    a.write(S)
+    b.write(S)
+    E = D.Ensemble([a])
+    for _ in range(3):
+        E.step(spec["dt"], spec["nsub"])
+        b.step(spec["dt"], spec["nsub"])
+    x, y = a.read(), b.read()
+    for k in FIELDS:
+        assert np.array_equal(x[k], y[k]), k
+    E.close()
+    a.close()
+    b.close()
+    with pytest.raises(D.DycoreError) as ei:
+        D.State(G, params=p_on, diffusion="surrogate")
+    assert ei.value.code == D.DC_EINVAL
+    G.close()
