@@ -28,5 +28,7 @@ def default_params():
         "hdiff_k4": 1.0 / 128.0,  # 4th-order background diffusion, k4 * A_e^2
         "diffuse_w": 1,         # apply 2nd-order Smagorinsky diffusion to w
         "diffuse_theta": 0,     # optional 2nd-order Smagorinsky diffusion of theta_v, exner updated
+        "theta_enh_nlev": 0,    # with diffuse_theta: lowest levels whose theta_v coefficient is raised
+        "theta_enh_thresh": 5.0,  # ... in cells colder than their neighbours' mean by more than this [K]
         "rd": RD, "cpd": CPD, "cvd": CVD, "omega": OMEGA,
     }

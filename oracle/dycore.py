@@ -257,6 +257,25 @@ def smagorinsky_nu(g, p, vv, dt):
     return np.minimum(p["smag_cs"] * g.a_e * deform, g.a_e / (p["smag_cap"] * dt))
 
 
+def near_surface_nu(g, p, th, dt):
+    """Section 4.1: the theta_v diffusion coefficient is raised where the
+    near-surface temperature contrast is strong.  Reading: a cell colder
+    than the mean of its three neighbours by more than the threshold T
+    (delta = theta_c - mean_n theta_n < -T; the reference profile is the
+    same in every cell of a level here, so it drops out) gets a floor on
+    its coefficient that grows linearly from 0 at delta = -T to the
+    stability cap at delta = -2T and stays there:
+        s = clip((-delta - T) / T, 0, 1),  floor = s * mean_e(A_e) / (smag_cap dt),
+    the cap being the one of the Smagorinsky viscosity, averaged over the
+    cell's edges like nu.  th holds the affected levels (the lowest ones)."""
+    mean_n = (th[:, g.c2e2c[:, 0]] + th[:, g.c2e2c[:, 1]] + th[:, g.c2e2c[:, 2]]) / 3.0
+    delta = th - mean_n
+    thr = p["theta_enh_thresh"]
+    s = np.clip((-delta - thr) / thr, 0.0, 1.0)
+    cap_c = (g.a_e[g.c2e[:, 0]] + g.a_e[g.c2e[:, 1]] + g.a_e[g.c2e[:, 2]]) / 3.0 / (p["smag_cap"] * dt)
+    return s * cap_c
+
+
 def diffusion(g, p, S, dt, wts=None):
     if wts is None:
         wts = vertex_lsq_weights(g)
@@ -282,6 +301,11 @@ def diffusion(g, p, S, dt, wts=None):
         # the equation of state linearised at fixed rho, dpi/pi = (R_d/c_vd)
         # dtheta_v/theta_v, so that pressure changes only at second order.
         nu_f = op.avg_c(g, nu)
+        n_enh = p.get("theta_enh_nlev", 0)
+        if n_enh > 0:
+            assert n_enh <= K
+            nu_f[K - n_enh:] = np.maximum(nu_f[K - n_enh:],
+                                          near_surface_nu(g, p, S["theta_v"][K - n_enh:], dt))
         dth = dt * nu_f * op.laps(g, S["theta_v"])
         out["theta_v"] = S["theta_v"] + dth
         out["exner"] = S["exner"] * (1.0 + p["rd"] / p["cvd"] * dth / S["theta_v"])

@@ -225,3 +225,58 @@ def test_theta_diffusion_maximum_principle_and_pressure(r2b3):
     resid = out["exner"] / S["exner"] - (1.0 + x) ** a
     assert np.max(np.abs(resid)) <= 0.2 * np.max(x * x) + 1e-15
     assert np.array_equal(out["rho"], S["rho"])
+
+
+def _cold_pool_increment(g, S, cell, level, d_theta, n_enh, p_extra=None):
+    """theta_v increment of `cell` at `level` after one diffusion step of a
+    resting state (vn = 0, so the Smagorinsky viscosity is zero everywhere)
+    whose theta_v is the reference column except at that one point, shifted
+    by d_theta.  Returns the increment, the output and the input."""
+    S = {k: v.copy() for k, v in S.items()}
+    S["theta_v"][level, cell] += d_theta
+    p = default_params()
+    p["diffuse_theta"] = 1
+    p["theta_enh_nlev"] = n_enh
+    p.update(p_extra or {})
+    out = dycore.diffusion(g, p, S, 600.0)
+    return out["theta_v"][level, cell] - S["theta_v"][level, cell], out, S
+
+
+def test_near_surface_enhancement_ramp_and_band(r2b3):
+    """The near-surface floor on the theta_v coefficient (Section 4.1): with
+    no wind only the floor diffuses.  A cold point anomaly -dT relaxes by
+    s(dT) * f * dT, s ramping from 0 at dT = T to 1 at dT = 2T; f, the
+    fraction one step at the stability cap removes, is geometry alone
+    (3 / (8 sqrt 3) on an equilateral mesh with A_e = l d / 2 and the cap
+    A_e / (16 dt)), so increment ratios between anomalies fix the ramp.  Warm
+    anomalies, anomalies above the band of lowest levels and the cold cell's
+    neighbours (warmer than their own neighbours) stay untouched."""
+    S, vert = initial_state(r2b3, 4, 10e3, seed=5)
+    g = Grid(r2b3, vert)
+    assert np.all(S["vn"] == 0.0) and np.all(np.ptp(S["theta_v"], axis=1) == 0.0)
+    T = default_params()["theta_enh_thresh"]
+    K, c = 4, 17
+    inc = {}
+    for m in (0.9, 1.5, 2.0, 3.0):
+        inc[m], out, S1 = _cold_pool_increment(g, S, c, K - 1, -m * T, 1)
+        # nothing else moves: every other cell has zero coefficient
+        mask = np.ones_like(S1["theta_v"], dtype=bool)
+        mask[K - 1, c] = False
+        assert np.array_equal(out["theta_v"][mask], S1["theta_v"][mask])
+    assert inc[0.9] == 0.0
+    f = inc[2.0] / (2.0 * T)
+    assert abs(f / (3.0 / (8.0 * np.sqrt(3.0))) - 1) < 0.15, f
+    assert abs(inc[3.0] / inc[2.0] - 1.5) < 1e-12  # s saturates at 1
+    assert abs(inc[1.5] / inc[2.0] - 0.375) < 1e-12  # s = 0.5 at dT = 1.5 T
+    # warm anomaly: no floor
+    assert _cold_pool_increment(g, S, c, K - 1, 3.0 * T, 1)[0] == 0.0
+    # the level above the band of one level is left alone; with a band of two
+    # it relaxes like the lowest level (same horizontal geometry)
+    assert _cold_pool_increment(g, S, c, K - 2, -3.0 * T, 1)[0] == 0.0
+    up = _cold_pool_increment(g, S, c, K - 2, -3.0 * T, 2)[0]
+    assert abs(up / inc[3.0] - 1) < 1e-12
+    # no overshoot past the surrounding value (the cap keeps f < 1)
+    assert 0.0 < f < 1.0
+    # a larger threshold moves the ramp: dT = 3 T with threshold 2 T gives s = 0.5
+    half = _cold_pool_increment(g, S, c, K - 1, -3.0 * T, 1, {"theta_enh_thresh": 2.0 * T})[0]
+    assert abs(half / inc[3.0] - 0.5) < 1e-12
