@@ -132,6 +132,13 @@ typedef struct {
                             at full levels with nu averaged over the cell's edges) and
                             moves exner with it, dpi/pi = (R_d/c_vd) dtheta_v/theta_v
                             (the equation of state at fixed rho); plain diffusion only */
+  int32_t theta_enh_nlev;   /* with diffuse_theta: in this many lowest levels (0..n_lev; 0 off)
+                               the theta_v coefficient of a cell colder than the mean of its
+                               three neighbours by dT > theta_enh_thresh is raised to at least
+                               s * mean_e(A_e) / (smag_cap * dt), s = min(1, dT / thresh - 1):
+                               the paper's larger coefficients for strong near-surface
+                               temperature contrasts (Section 4.1)                        */
+  double theta_enh_thresh;  /* that threshold [K] (> 0; 5)                                     */
 } dc_params;
 
 /* Device pointers of the five prognostic fields, [level][entity] padded.

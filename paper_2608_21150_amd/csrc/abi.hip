@@ -262,6 +262,8 @@ dc_status dc_params_default(dc_params* p) {
   p->diffuse_w = 1;
   p->check_finite = 0;
   p->diffuse_theta = 0;
+  p->theta_enh_nlev = 0;
+  p->theta_enh_thresh = 5.0;
   return DC_OK;
 }
 
@@ -369,6 +371,11 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
       !(p.rayleigh_zfrac > 0 && p.rayleigh_zfrac < 1) || p.rayleigh_tau0 < 0 || p.divdamp_c4 < 0 || p.hdiff_k4 < 0 ||
       p.smag_cs < 0 || !std::isfinite(p.omega) || (p.diffuse_theta != 0 && p.diffuse_theta != 1))
     return fail(DC_EINVAL, "parameter out of range");
+  if (p.theta_enh_nlev < 0 || p.theta_enh_nlev > g->h.K || !(p.theta_enh_thresh > 0) ||
+      !std::isfinite(p.theta_enh_thresh))
+    return fail(DC_EINVAL, "theta_enh_nlev must lie in 0..n_lev and theta_enh_thresh be positive");
+  if (p.theta_enh_nlev > 0 && !p.diffuse_theta)
+    return fail(DC_EINVAL, "theta_enh_nlev needs diffuse_theta");
   if (p.diffuse_theta && diff == DC_DIFF_SURROGATE)
     return fail(DC_EINVAL, "theta_v diffusion is available with the plain diffusion only");
   dc_status st = ensure_uploaded(g);

@@ -1021,6 +1021,13 @@ struct BDcv2 {
       lq.load(g, c);
       const int* ie = dq.ie;
       const int k0 = by * kb, k1 = min(K + 1, k0 + kb);
+      // near-surface floor on the theta_v coefficient: the Smagorinsky
+      // stability cap averaged over the cell's edges, reached by cells
+      // colder than their neighbours' mean by twice the threshold
+      const int k_enh = K - cf.theta_enh_nlev;
+      double capc = 0.0;
+      if (cf.diffuse_theta && k1 > k_enh)
+        capc = (g.ae[ie[0]] + g.ae[ie[1]] + g.ae[ie[2]]) / 3.0 / (cf.cap * cf.dt);
       // nu on the cell's edges at full level k - 1, carried from one half
       // level to the next
       R nup[3] = {R(0), R(0), R(0)};
@@ -1043,10 +1050,19 @@ struct BDcv2 {
             const double* tr = args.th_in + (size_t)k * g.cs;
             const double tc = tr[c];
             const R nuf = (nuk[0] + nuk[1] + nuk[2]) / R(3);
+            double nud = (double)nuf;
+            double tn[3];
+  #pragma unroll
+            for (int i = 0; i < 3; ++i) tn[i] = tr[lq.nb[i]];
+            if (k >= k_enh) {
+              const double cold = (tn[0] + tn[1] + tn[2]) / 3.0 - tc;
+              const double sr = fmin(fmax((cold - cf.theta_enh_thr) / cf.theta_enh_thr, 0.0), 1.0);
+              nud = fmax(nud, sr * capc);
+            }
             double lt = 0.0;
   #pragma unroll
-            for (int i = 0; i < 3; ++i) lt += lq.kl[i] * (tr[lq.nb[i]] - tc);
-            const double dth = cf.dt * (double)nuf * lt;
+            for (int i = 0; i < 3; ++i) lt += lq.kl[i] * (tn[i] - tc);
+            const double dth = cf.dt * nud * lt;
             args.th_out[r] = tc + dth;
             args.ex[r] = args.ex[r] * (1.0 + cf.rd_cvd * dth / tc);
           }

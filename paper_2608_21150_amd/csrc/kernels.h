@@ -76,6 +76,8 @@ struct Tile {
 struct StepCoef {
   double dtau, dt, eta, a0, a1, cpd, rd_cvd, cvd_rd, c4a2, cs, cap, k4;
   int diffuse_w, diffuse_theta;
+  int theta_enh_nlev;    // lowest levels with the near-surface floor on the theta_v coefficient
+  double theta_enh_thr;  // its threshold [K]
 };
 
 // Pointers of one predictor/corrector/diffusion pass; the meaning of each

@@ -78,6 +78,8 @@ inline StepCoef make_coef(const dc_state* s, double dt, int nsub) {
   c.k4 = s->p.hdiff_k4;
   c.diffuse_w = s->p.diffuse_w;
   c.diffuse_theta = s->p.diffuse_theta;
+  c.theta_enh_nlev = s->p.theta_enh_nlev;
+  c.theta_enh_thr = s->p.theta_enh_thresh;
   return c;
 }
 

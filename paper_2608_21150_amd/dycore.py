@@ -59,7 +59,8 @@ class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("eta", "adv_w0", "adv_w1", "divdamp_c4", "rayleigh_tau0", "rayleigh_zfrac", "smag_cs",
                  "smag_cap", "hdiff_k4", "rd", "cpd", "cvd", "omega")] + [
-        ("diffuse_w", ctypes.c_int32), ("check_finite", ctypes.c_int32), ("diffuse_theta", ctypes.c_int32)]
+        ("diffuse_w", ctypes.c_int32), ("check_finite", ctypes.c_int32), ("diffuse_theta", ctypes.c_int32),
+        ("theta_enh_nlev", ctypes.c_int32), ("theta_enh_thresh", ctypes.c_double)]
 
 
 class Fields(ctypes.Structure):

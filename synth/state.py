@@ -139,3 +139,21 @@ def initial_state(
     state = {"vn": vn, "w": w, "rho": rho, "exner": exner, "theta_v": theta_v}
     vert = {"z_half": z_half, "z_full": z_full, **ref}
     return state, vert
+
+
+def add_cold_pools(state, n_cells: int, n_levels: int, d_theta: float, seed: int):
+    """Copy of `state` with cold pools: n_cells cells drawn without
+    replacement (PCG64 with `seed`) have theta_v lowered by d_theta in their
+    n_levels lowest levels, rho raised so that rho * theta_v, and with it the
+    pressure and exner of the equation of state, is unchanged.  Strong
+    near-surface temperature contrasts of this kind are what the diffusion's
+    near-surface coefficient floor acts on."""
+    out = {k: v.copy() for k, v in state.items()}
+    n_lev, nc = out["rho"].shape
+    cells = np.random.default_rng(seed).choice(nc, n_cells, replace=False)
+    for k in range(n_lev - n_levels, n_lev):
+        th = out["theta_v"][k, cells]
+        cold = th - d_theta
+        out["rho"][k, cells] *= th / cold
+        out["theta_v"][k, cells] = cold
+    return out

@@ -19,7 +19,7 @@ from paper_2608_21150_amd import dycore as D  # noqa: E402
 from oracle import dycore as O  # noqa: E402
 from oracle.constants import default_params  # noqa: E402
 from oracle.grid import Grid as OGrid  # noqa: E402
-from synth import build_workload, initial_state, make_grid  # noqa: E402
+from synth import add_cold_pools, build_workload, initial_state, make_grid  # noqa: E402
 
 FIELDS = ("vn", "w", "rho", "exner", "theta_v")
 
@@ -248,4 +248,66 @@ def test_theta_diffusion_parity_and_batching():
     with pytest.raises(D.DycoreError) as ei:
         D.State(G, params=p_on, diffusion="surrogate")
     assert ei.value.code == D.DC_EINVAL
+    G.close()
+
+
+def test_near_surface_enhancement_parity():
+    """The near-surface floor on the theta_v coefficient with the theta_v
+    diffusion: config 1's state with 40 cold pools (12 K colder in the three
+    lowest levels, pressure unchanged) so that the floor acts; three steps
+    with the floor in the four lowest levels, FP64 against the oracle with
+    the same options; the floor changes the result; mixed precision stays
+    close; in an ensemble next to a member without the floor both equal
+    their solo runs bit for bit; out-of-range settings are refused."""
+    g0, S0, vert, spec = build_workload("r2b2_k30")
+    S = add_cold_pools(S0, 40, 3, 12.0, seed=7)
+    steps = 3
+    p_on = D.default_params(diffuse_theta=1, theta_enh_nlev=4)
+    p_off = D.default_params(diffuse_theta=1)
+    out, d = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], steps, params=p_on)
+    assert d["n_nonfinite"] == 0
+    og = OGrid(g0, vert)
+    wts = O.vertex_lsq_weights(og)
+    po = default_params()
+    po["diffuse_theta"] = 1
+    po["theta_enh_nlev"] = 4
+    ref = S
+    for _ in range(steps):
+        ref = O.step(og, ref, spec["dt"], spec["nsub"], po, diffuse=True, wts=wts)
+    errs = {k: rel_l2(out[k], ref[k]) for k in FIELDS}
+    print("near-surface floor, rel L2 vs oracle:", errs)
+    for k in FIELDS:
+        assert errs[k] <= 1e-11, (k, errs[k])
+    off, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], steps, params=p_off)
+    assert rel_l2(out["theta_v"], off["theta_v"]) > 1e-6
+    mixed, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], steps, precision="mixed", params=p_on)
+    for k in ("vn", "rho", "exner", "theta_v"):
+        assert rel_l2(mixed[k], out[k]) <= 1e-4, k
+    G = D.Grid(g0, vert)
+    members = [D.State(G, params=p_on), D.State(G, params=p_off)]
+    solos = [D.State(G, params=p_on), D.State(G, params=p_off)]
+    for st in members + solos:
+        st.write(S)
+    E = D.Ensemble(members)
+    for _ in range(2):
+        E.step(spec["dt"], spec["nsub"])
+        for st in solos:
+            st.step(spec["dt"], spec["nsub"])
+    for a, b in zip(members, solos):
+        x, y = a.read(), b.read()
+        for k in FIELDS:
+            assert np.array_equal(x[k], y[k]), k
+    E.close()
+    for st in members + solos:
+        st.close()
+    K = S["rho"].shape[0]
+    bad = [dict(diffuse_theta=1, theta_enh_nlev=K + 1), dict(diffuse_theta=1, theta_enh_nlev=-1),
+           dict(diffuse_theta=0, theta_enh_nlev=2), dict(diffuse_theta=1, theta_enh_nlev=2, theta_enh_thresh=0.0),
+           dict(diffuse_theta=1, theta_enh_nlev=2, theta_enh_thresh=float("nan"))]
+    for kw in bad:
+        with pytest.raises(D.DycoreError) as ei:
+            D.State(G, params=D.default_params(**kw))
+        assert ei.value.code == D.DC_EINVAL, kw
+    st = D.State(G, params=D.default_params(diffuse_theta=1, theta_enh_nlev=K))  # every level: allowed
+    st.close()
     G.close()
