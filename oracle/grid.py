@@ -22,11 +22,20 @@ Canonical rules, applied to the (possibly renumbered) input tables:
                circulation sign).
   e2c2e[e]   = [c2e(c0) without e, in c2e order] ++ [c2e(c1) without e].
   e2c2v[e]   = [v0, v1, vertex of c0 off e, vertex of c1 off e].
-SFC renumbering (optional): cells sorted by (Morton key, old id), the key
-interleaving q(x), q(y), q(z) of the unit circumcentre with
-q(u) = floor((u + 1) * 0.5 * (2^21 - 1)), x in the top bit of each triple;
+SFC renumbering (optional): cells sorted by (triangle-tree key, old id);
 edges sorted by (min new cell, max new cell, old id); vertices by
-(min new id of the cells around it, old id).
+(min new id of the cells around it, old id).  The key of a unit vector x
+walks a recursive subdivision of a fixed icosahedron (poles on the z axis,
+the upper ring at longitudes 72 i degrees and z = 1/sqrt 5, the lower ring
+36 degrees further and z = -1/sqrt 5): the face is the one whose smallest
+great-circle side test det(x, B, C), det(A, x, C), det(A, B, x) is largest
+(the first on ties); then, 16 times, the triangle (A, B, C) is split at the
+normalised midpoints ab, bc, ca into the corner children (A, ab, ca),
+(ab, B, bc), (ca, bc, C), taken when x lies inside the first of them
+(det(x, ab, ca), det(x, bc, ab), det(x, ca, bc) > 0, tested in that order),
+else the middle child (ab, bc, ca); key = face * 4^16 + the base-4 digits of
+the children.  Blocks of 4^j consecutive keys are spherical triangles, so a
+block of cells touches few cache lines of its neighbours' data.
 """
 from __future__ import annotations
 
@@ -40,20 +49,68 @@ def _common(a, b):
     return np.where(m00 | m01, a[:, 0], a[:, 1])
 
 
-def morton_key(xyz):
-    q = np.floor((xyz + 1.0) * 0.5 * 2097151.0).astype(np.uint64)
-    key = np.zeros(xyz.shape[0], dtype=np.uint64)
-    for bit in range(21):
-        for axis, shift in ((0, 2), (1, 1), (2, 0)):
-            b = (q[:, axis] >> np.uint64(bit)) & np.uint64(1)
-            key |= b << np.uint64(3 * bit + shift)
+def _ico():
+    """The icosahedron of the tree key: 12 unit vertices, 20 faces
+    counter-clockwise seen from outside (written out with square roots only,
+    so that every implementation builds the same bits)."""
+    s5 = np.sqrt(5.0)
+    c1, s1 = (s5 - 1.0) / 2.0, np.sqrt(10.0 + 2.0 * s5) / 2.0  # 2 cos 72, 2 sin 72
+    c2, s2 = (s5 + 1.0) / 2.0, np.sqrt(10.0 - 2.0 * s5) / 2.0  # 2 cos 36, 2 sin 36
+    v = np.array([[0.0, 0.0, s5],
+                  [2.0, 0.0, 1.0], [c1, s1, 1.0], [-c2, s2, 1.0], [-c2, -s2, 1.0], [c1, -s1, 1.0],
+                  [c2, s2, -1.0], [-c1, s1, -1.0], [-2.0, 0.0, -1.0], [-c1, -s1, -1.0], [c2, -s2, -1.0],
+                  [0.0, 0.0, -s5]]) / s5
+    faces = np.array([[0, 1, 2], [1, 6, 2], [2, 6, 7], [11, 7, 6], [0, 2, 3], [2, 7, 3], [3, 7, 8],
+                      [11, 8, 7], [0, 3, 4], [3, 8, 4], [4, 8, 9], [11, 9, 8], [0, 4, 5], [4, 9, 5],
+                      [5, 9, 10], [11, 10, 9], [0, 5, 1], [5, 10, 1], [1, 10, 6], [11, 6, 10]])
+    return v, faces
+
+
+TREE_LEVELS = 16
+
+
+def _det(a, b, c):
+    """a . (b x c), summed in this order."""
+    return ((a[..., 0] * (b[..., 1] * c[..., 2] - b[..., 2] * c[..., 1])
+             + a[..., 1] * (b[..., 2] * c[..., 0] - b[..., 0] * c[..., 2]))
+            + a[..., 2] * (b[..., 0] * c[..., 1] - b[..., 1] * c[..., 0]))
+
+
+def _mid(p, q):
+    s = p + q
+    return s / np.sqrt((s[..., 0] * s[..., 0] + s[..., 1] * s[..., 1]) + s[..., 2] * s[..., 2])[..., None]
+
+
+def tree_key(xyz):
+    """Triangle-tree key (int64) of each row of xyz (any positive length:
+    every decision is the sign or the order of triple products with x)."""
+    v, faces = _ico()
+    n = xyz.shape[0]
+    best = np.full(n, -np.inf)
+    face = np.zeros(n, dtype=np.int64)
+    for f in range(20):
+        a, b, c = v[faces[f, 0]], v[faces[f, 1]], v[faces[f, 2]]
+        m = np.minimum(np.minimum(_det(xyz, b, c), _det(a, xyz, c)), _det(a, b, xyz))
+        up = m > best
+        best[up] = m[up]
+        face[up] = f
+    a, b, c = v[faces[face, 0]], v[faces[face, 1]], v[faces[face, 2]]
+    key = face.copy()
+    for _ in range(TREE_LEVELS):
+        ab, bc, ca = _mid(a, b), _mid(b, c), _mid(c, a)
+        ch = np.where(_det(xyz, ab, ca) > 0, 0,
+                      np.where(_det(xyz, bc, ab) > 0, 1, np.where(_det(xyz, ca, bc) > 0, 2, 3)))[:, None]
+        a, b, c = (np.where(ch == 0, a, np.where(ch == 1, ab, np.where(ch == 2, ca, ab))),
+                   np.where(ch == 0, ab, np.where(ch == 1, b, bc)),
+                   np.where(ch == 0, ca, np.where(ch == 1, bc, np.where(ch == 2, c, ca))))
+        key = key * 4 + ch[:, 0]
     return key
 
 
 def sfc_permutation(g):
     """Return new->old permutations (cells, edges, vertices)."""
     nc, ne, nv = g["n_cells"], g["n_edges"], g["n_verts"]
-    key = morton_key(g["cell_xyz"])
+    key = tree_key(g["cell_xyz"])
     pc = np.lexsort((np.arange(nc), key))
     old2new_c = np.empty(nc, dtype=np.int64)
     old2new_c[pc] = np.arange(nc)

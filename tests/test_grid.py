@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from synth import expected_counts
-from oracle.grid import derive, morton_key, renumber, sfc_permutation
+from oracle.grid import TREE_LEVELS, _ico, derive, renumber, sfc_permutation, tree_key
 
 SMALL = [(1, 0), (2, 0), (2, 1), (2, 2)]
 
@@ -124,19 +124,87 @@ def test_counter_clockwise_orders(grids, n, k):
         assert abs(total - 2 * np.pi) < 1e-6
 
 
-def test_morton_key_brute_force():
-    rng = np.random.default_rng(3)
-    x = rng.normal(size=(50, 3))
-    x /= np.linalg.norm(x, axis=1, keepdims=True)
-    keys = morton_key(x)
-    for row, key in zip(x, keys):
-        q = [int(np.floor((u + 1.0) * 0.5 * 2097151.0)) for u in row]
-        want = 0
-        for bit in range(21):
-            for axis, shift in ((0, 2), (1, 1), (2, 0)):
-                want |= ((q[axis] >> bit) & 1) << (3 * bit + shift)
-        assert int(key) == want
-        assert want < 2**63
+def test_tree_icosahedron_is_regular():
+    """The key's icosahedron: 12 unit vertices with the poles on the z axis
+    and the rings at latitude +-atan(1/2), longitudes 72 i and 72 i + 36
+    degrees; 30 edges of one length (the central angle atan 2), each shared
+    by two faces; all 20 faces counter-clockwise seen from outside."""
+    v, faces = _ico()
+    assert np.allclose(np.linalg.norm(v, axis=1), 1.0, atol=1e-15)
+    assert np.allclose(v[0], [0, 0, 1]) and np.allclose(v[11], [0, 0, -1])
+    lon = np.degrees(np.arctan2(v[1:11, 1], v[1:11, 0])) % 360.0
+    assert np.allclose(lon[:5], [0, 72, 144, 216, 288]) and np.allclose(lon[5:], [36, 108, 180, 252, 324])
+    assert np.allclose(np.abs(np.arcsin(v[1:11, 2])), np.arctan(0.5))
+    edges = {}
+    for f in faces:
+        a, b, c = v[f]
+        assert np.dot(np.cross(b - a, c - a), a + b + c) > 0
+        for i in range(3):
+            e = tuple(sorted((f[i], f[(i + 1) % 3])))
+            edges[e] = edges.get(e, 0) + 1
+    assert len(edges) == 30 and set(edges.values()) == {2}
+    ang = [np.arccos(np.clip(np.dot(v[i], v[j]), -1, 1)) for i, j in edges]
+    assert np.allclose(ang, np.arctan(2.0))
+
+
+def _leaves(depth):
+    """Brute force: every triangle of the subdivided icosahedron `depth`
+    levels down, as (centroid direction, face, child digits), built by plain
+    recursion over explicit triangles."""
+    v, faces = _ico()
+    out = []
+
+    def rec(a, b, c, face, digits, d):
+        if d == 0:
+            g = a + b + c
+            out.append((g / np.linalg.norm(g), face, digits))
+            return
+        m = lambda p, q: (p + q) / np.linalg.norm(p + q)
+        ab, bc, ca = m(a, b), m(b, c), m(c, a)
+        for i, (x, y, z) in enumerate(((a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca))):
+            rec(x, y, z, face, digits + [i], d - 1)
+
+    for f, (i, j, k) in enumerate(faces):
+        rec(v[i], v[j], v[k], f, [], depth)
+    return out
+
+
+def test_tree_key_against_explicit_subdivision():
+    """The key of each leaf triangle's centroid, three levels down, starts
+    with that leaf's face and child digits; every face centroid stays in the
+    middle child at all levels (the middle child of an equilateral spherical
+    triangle shares its centre), so its digits are all 3."""
+    leaves = _leaves(3)
+    keys = tree_key(np.array([x for x, _, _ in leaves]))
+    shift = 2 * (TREE_LEVELS - 3)
+    for key, (_, f, d) in zip(keys.tolist(), leaves):
+        assert key >> shift == ((f * 4 + d[0]) * 4 + d[1]) * 4 + d[2]
+    v, faces = _ico()
+    cen = v[faces].sum(axis=1)
+    assert (tree_key(cen) == np.arange(20) * 4**TREE_LEVELS + (4**TREE_LEVELS - 1)).all()
+    # positive scaling of x does not change the key
+    assert (tree_key(7.0 * cen) == tree_key(cen)).all()
+
+
+def test_sfc_blocks_are_compact(grids):
+    """Runs of 64 = 4^3 consecutive cells in the curve's order are connected
+    patches of the mesh (over c2e2c), as the locality of neighbour gathers
+    needs."""
+    g = grids(2, 3)
+    pc, _, _ = sfc_permutation(g)
+    oc = np.empty_like(pc)
+    oc[pc] = np.arange(pc.size)
+    nb = oc[g["c2e2c"]]
+    for b0 in range(0, pc.size, 64):
+        members = set(range(b0, b0 + 64))
+        seen, stack = {b0}, [b0]
+        while stack:
+            c = stack.pop()
+            for n in nb[pc[c]]:
+                if n in members and n not in seen:
+                    seen.add(int(n))
+                    stack.append(int(n))
+        assert len(seen) == 64, b0
 
 
 @pytest.mark.parametrize("n,k", [(2, 1), (2, 2)])
@@ -145,8 +213,8 @@ def test_sfc_renumbering(grids, n, k):
     pc, pe, pv = sfc_permutation(g)
     for p, m in ((pc, g["n_cells"]), (pe, g["n_edges"]), (pv, g["n_verts"])):
         assert np.array_equal(np.sort(p), np.arange(m))
-    keys = morton_key(g["cell_xyz"][pc])
-    assert (np.diff(keys.astype(np.float64)) >= 0).all()
+    keys = tree_key(g["cell_xyz"][pc])
+    assert (np.diff(keys) >= 0).all()
     h = renumber(g, pc, pe, pv)
     d = derive(h)  # renumbered grid is still a consistent grid
     assert abs(h["cell_area"].sum() - g["cell_area"].sum()) / g["cell_area"].sum() < 1e-13
