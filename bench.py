@@ -371,7 +371,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="r2b5_k65")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--sfc", type=int, default=-1, help="1/0 force the Morton renumbering; -1 workload default")
+    ap.add_argument("--sfc", type=int, default=-1, help="1/0 force the space-filling-curve renumbering; -1 workload default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-steps", type=int, default=200, help="surrogate: plain steps that collect pairs")
     ap.add_argument("--train-per-step", type=int, default=1_000_000, help="surrogate: pairs per collected step")
@@ -497,7 +497,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: R{g0['n']}B{g0['k']} icosahedral grid, {C} cells, {E} edges, "
                                f"{V} vertices, {K} levels, dt {spec['dt']} s, {spec['nsub']} substeps, "
-                               f"{'Morton-ordered' if sfc else 'generator-ordered'}, {args.precision}",
+                               f"{'curve-ordered' if sfc else 'generator-ordered'}, {args.precision}",
                    "cells": C, "levels": K, "dt": spec["dt"], "nsub": spec["nsub"], "precision": args.precision,
                    "tiles": {k: f"{t}x{l}" for k, (t, l) in R1["tiles"].items()},
                    "autotune_s": None if R1["tune_s"] is None else round(R1["tune_s"], 2)},

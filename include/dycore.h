@@ -71,8 +71,11 @@ typedef enum { DC_DIFF_PLAIN = 0, DC_DIFF_SURROGATE = 1, DC_DIFF_NONE = 2 } dc_d
  *   z_half [K+1] strictly decreasing; exner_ref_full, theta_ref_full [K];
  *   theta_ref_half, dexner_dz_ref_half [K+1]: the reference atmosphere
  *   (pi0, theta0 at full levels, theta0 and d pi0/dz at half levels).
- * sfc_reorder = 1 renumbers cells, edges and vertices along a Morton curve of
- * the circumcentres (locality of neighbour gathers).  Host arrays passed to
+ * sfc_reorder = 1 renumbers cells, edges and vertices along a space-filling
+ * curve of the circumcentres for locality of the neighbour gathers: the keys
+ * descend a recursive 4-way subdivision of a fixed icosahedron (poles on the
+ * z axis), so runs of 4^j consecutive cells are spherical triangles; edges
+ * follow their lower new cell, vertices the lowest new cell around them.  Host arrays passed to
  * dc_state_read/write always use the caller's original numbering.
  */
 typedef struct {

@@ -1,4 +1,4 @@
-// Host grid layer: validation, optional Morton renumbering, canonical
+// Host grid layer: validation, optional space-filling-curve renumbering, canonical
 // connectivity, orientation signs and stencil coefficients.
 //
 // Neighbour access on the icosahedral grid goes through index lookup tables
@@ -13,12 +13,17 @@
 //   v2c[v][i]  cell between v2e[v][i] and v2e[v][i+1]
 //   e2c2e[e]   other edges of c0 then of c1, in c2e order
 //   e2c2v[e]   v0, v1, vertex of c0 off e, vertex of c1 off e
-// Morton renumbering: cells by (key, id), key interleaving
-// q(u) = floor((u + 1) * 0.5 * (2^21 - 1)) of the unit circumcentre with x in
-// the top bit of each triple; edges by (min new cell, max new cell, id);
-// vertices by (min new id of their cells, id).
+// Space-filling-curve renumbering: cells by (triangle-tree key, id), edges
+// by (min new cell, max new cell, id), vertices by (min new id of their
+// cells, id).  The key descends a recursive subdivision of a fixed
+// icosahedron (poles on the z axis, rings at z = +-1/sqrt 5, longitudes 72 i
+// and 72 i + 36 degrees): the face whose smallest great-circle side test is
+// largest, then 16 levels of 4-way splits at normalised edge midpoints
+// (corner children first, the middle child otherwise), two bits per level.
+// Runs of 4^j consecutive keys are spherical triangles: a 64-cell block of
+// a subdivided icosahedral grid is one compact patch.
 // This file is compiled without floating-point contraction so that the
-// floating-point decisions above (orientation tests, Morton quantisation)
+// floating-point decisions above (orientation tests, the tree's side tests)
 // are taken exactly as written.
 
 #include <algorithm>
@@ -44,15 +49,65 @@ inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
 
-uint64_t morton(V3 u) {
-  const double c[3] = {u.x, u.y, u.z};
-  uint64_t q[3];
-  for (int a = 0; a < 3; ++a) q[a] = (uint64_t)std::floor((c[a] + 1.0) * 0.5 * 2097151.0);
-  uint64_t key = 0;
-  for (int bit = 0; bit < 21; ++bit) {
-    key |= ((q[0] >> bit) & 1ull) << (3 * bit + 2);
-    key |= ((q[1] >> bit) & 1ull) << (3 * bit + 1);
-    key |= ((q[2] >> bit) & 1ull) << (3 * bit + 0);
+// a . (b x c), summed in this order
+inline double det3(V3 a, V3 b, V3 c) {
+  return (a.x * (b.y * c.z - b.z * c.y) + a.y * (b.z * c.x - b.x * c.z)) + a.z * (b.x * c.y - b.y * c.x);
+}
+inline V3 mid(V3 p, V3 q) {
+  const V3 s = add(p, q);
+  const double n = std::sqrt((s.x * s.x + s.y * s.y) + s.z * s.z);
+  return {s.x / n, s.y / n, s.z / n};
+}
+
+constexpr int kTreeLevels = 16;
+
+uint64_t tree_key(V3 x) {
+  const double s5 = std::sqrt(5.0);
+  const double c1 = (s5 - 1.0) / 2.0, s1 = std::sqrt(10.0 + 2.0 * s5) / 2.0;  // 2 cos 72, 2 sin 72
+  const double c2 = (s5 + 1.0) / 2.0, s2 = std::sqrt(10.0 - 2.0 * s5) / 2.0;  // 2 cos 36, 2 sin 36
+  const double raw[12][3] = {{0.0, 0.0, s5},  {2.0, 0.0, 1.0},  {c1, s1, 1.0},    {-c2, s2, 1.0},
+                             {-c2, -s2, 1.0}, {c1, -s1, 1.0},   {c2, s2, -1.0},   {-c1, s1, -1.0},
+                             {-2.0, 0.0, -1.0}, {-c1, -s1, -1.0}, {c2, -s2, -1.0}, {0.0, 0.0, -s5}};
+  static const int faces[20][3] = {{0, 1, 2},  {1, 6, 2},  {2, 6, 7},  {11, 7, 6}, {0, 2, 3},
+                                   {2, 7, 3},  {3, 7, 8},  {11, 8, 7}, {0, 3, 4},  {3, 8, 4},
+                                   {4, 8, 9},  {11, 9, 8}, {0, 4, 5},  {4, 9, 5},  {5, 9, 10},
+                                   {11, 10, 9}, {0, 5, 1}, {5, 10, 1}, {1, 10, 6}, {11, 6, 10}};
+  V3 v[12];
+  for (int i = 0; i < 12; ++i) v[i] = {raw[i][0] / s5, raw[i][1] / s5, raw[i][2] / s5};
+  int face = 0;
+  double best = -INFINITY;
+  for (int f = 0; f < 20; ++f) {
+    const V3 a = v[faces[f][0]], b = v[faces[f][1]], c = v[faces[f][2]];
+    const double m = std::min(std::min(det3(x, b, c), det3(a, x, c)), det3(a, b, x));
+    if (m > best) {
+      best = m;
+      face = f;
+    }
+  }
+  V3 a = v[faces[face][0]], b = v[faces[face][1]], c = v[faces[face][2]];
+  uint64_t key = (uint64_t)face;
+  for (int l = 0; l < kTreeLevels; ++l) {
+    const V3 ab = mid(a, b), bc = mid(b, c), ca = mid(c, a);
+    int ch;
+    if (det3(x, ab, ca) > 0) {
+      ch = 0;
+      b = ab;
+      c = ca;
+    } else if (det3(x, bc, ab) > 0) {
+      ch = 1;
+      a = ab;
+      c = bc;
+    } else if (det3(x, ca, bc) > 0) {
+      ch = 2;
+      a = ca;
+      b = bc;
+    } else {
+      ch = 3;
+      a = ab;
+      b = bc;
+      c = ca;
+    }
+    key = key * 4 + (uint64_t)ch;
   }
   return key;
 }
@@ -193,14 +248,14 @@ int build_host_grid(const dc_grid_desc* D, HostGrid* g, std::string* err) {
   g->radius = D->radius;
   g->mean_area = 4.0 * M_PI * D->radius * D->radius / nc;
 
-  // ---- optional Morton renumbering (permutations internal -> original) ----
+  // ---- optional space-filling-curve renumbering (permutations internal -> original) ----
   std::vector<int32_t> pc(nc), pe(ne), pv(nv);
   std::iota(pc.begin(), pc.end(), 0);
   std::iota(pe.begin(), pe.end(), 0);
   std::iota(pv.begin(), pv.end(), 0);
   if (D->sfc_reorder) {
     std::vector<uint64_t> key(nc);
-    for (int c = 0; c < nc; ++c) key[c] = morton({D->cell_xyz[3 * c], D->cell_xyz[3 * c + 1], D->cell_xyz[3 * c + 2]});
+    for (int c = 0; c < nc; ++c) key[c] = tree_key({D->cell_xyz[3 * c], D->cell_xyz[3 * c + 1], D->cell_xyz[3 * c + 2]});
     std::stable_sort(pc.begin(), pc.end(), [&](int a, int b) { return key[a] < key[b]; });
     std::vector<int32_t> oc(nc);
     for (int i = 0; i < nc; ++i) oc[pc[i]] = i;
