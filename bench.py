@@ -126,8 +126,14 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, o
              f"counter calibration (`python bench.py --calibrate-copy 1024`, a 1 GiB device-to-device copy): "
              f"FETCH_SIZE reads {cF[copy]:.0f} KiB and WRITE_SIZE {cW[[k for k in cW if 'copyBuffer' in k][0]]:.0f} "
              f"KiB per {kib} KiB moved -> scale fetch x{sf:.3f}, write x{sw:.3f}", "",
-             "| kernel | id | calls | avg us | share % | FETCH KiB raw | WRITE KiB raw | HBM MB/launch (scaled) |",
-             "|---|---|---|---|---|---|---|---|"]
+             "| kernel | id | calls | avg us | share % | FETCH KiB raw | WRITE KiB raw | HBM MB/launch (scaled) "
+             "| HBM GB/s (counters) | algorithmic MB/launch | algorithmic GB/s |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
+    from synth import WORKLOADS, expected_counts
+
+    wl = WORKLOADS[workload]
+    C, E, V = expected_counts(wl["n"], wl["k"])
+    alg = kernel_bytes(C, E, V, wl["n_lev"], 4 if precision == "mixed" else 8)
     per = {}
     for r in rows:
         name = r["Name"]
@@ -136,9 +142,14 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, o
         kid = kernel_id(name)
         if kid and mb is not None:
             per[kid] = {"bytes": mb * 1e6, "avg_us": float(r["AverageNs"]) / 1e3}
-        lines.append(f"| {short(name)[:90]} | {kid or '-'} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+        us = float(r["AverageNs"]) / 1e3
+        gbs = "-" if mb is None or us <= 0 else f"{mb / us * 1e3:.0f}"
+        amb = alg.get(kid) / 1e6 if kid in alg else None
+        ags = "-" if amb is None or us <= 0 else f"{amb / us * 1e3:.0f}"
+        lines.append(f"| {short(name)[:90]} | {kid or '-'} | {r['Calls']} | {us:.1f} | "
                      f"{float(r['Percentage']):.2f} | {f if f is None else round(f, 1)} | "
-                     f"{w if w is None else round(w, 1)} | {'-' if mb is None else round(mb, 1)} |")
+                     f"{w if w is None else round(w, 1)} | {'-' if mb is None else round(mb, 1)} | {gbs} | "
+                     f"{'-' if amb is None else round(amb, 1)} | {ags} |")
     meta = {"workload": workload, "precision": precision, "sources_sha256": sources_sha256(),
             "fetch_scale": sf, "write_scale": sw, "kernels": per}
     lines += ["", "<!-- traffic " + json.dumps(meta) + " -->"]
