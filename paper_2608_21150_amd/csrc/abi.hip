@@ -73,7 +73,7 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff)
   L.wstar = take(K1 * h.cs * 8);
   L.wtmp = take(K1 * h.cs * 8);
   L.ttmp = take(K * h.cs * 8);  // theta_v staged for its diffusion
-  L.tw0 = take(K1 * h.cs * 8);
+  L.tw0 = take(K1 * h.cs * r);
   L.fe = take(h.es * 8);
   L.tau = take(K1 * 8);
   const int nblk = (h.nc + 255) / 256 + (h.ne + 255) / 256;
@@ -408,7 +408,7 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->wstar = reinterpret_cast<double*>(w + L.wstar);
   s->wtmp = reinterpret_cast<double*>(w + L.wtmp);
   s->ttmp = reinterpret_cast<double*>(w + L.ttmp);
-  s->tw0 = reinterpret_cast<double*>(w + L.tw0);
+  s->tw0 = w + L.tw0;
   s->fe = reinterpret_cast<double*>(w + L.fe);
   s->tau = reinterpret_cast<double*>(w + L.tau);
   s->diag_part = reinterpret_cast<double*>(w + L.dpart);

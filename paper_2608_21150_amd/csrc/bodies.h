@@ -316,7 +316,8 @@ struct ColArgs {
   const double *w, *rho, *ex, *th;  // state at the start of the substep
   const R* gw;                       // edge terms of T_w of this pass (from the edge kernel)
   const R* vnf;                      // vn of the mass fluxes (vn* / new vn)
-  double* tw0;                       // T_w at the substep start: written (predictor), read (corrector)
+  R* tw0;                            // T_w at the substep start: written (predictor), read (corrector);
+                                     // T_w is formed in R, so R storage is exact
   R* dv_out;                         // predictor: D = div vn* at the full levels
   const double* ws;                  // corrector: predicted w* (T_w*)
   double *w_out, *rho_out, *ex_out, *th_out;
@@ -389,7 +390,7 @@ struct BCol {
                                               const double* __restrict__ pw, const double* __restrict__ prho,
                                               const double* __restrict__ pex, const double* __restrict__ pth,
                                               const R* __restrict__ pgw, const R* __restrict__ pvn,
-                                              double* __restrict__ ptw0, R* __restrict__ pdv,
+                                              R* __restrict__ ptw0, R* __restrict__ pdv,
                                               const double* __restrict__ pws, double* __restrict__ pw_out,
                                               double* __restrict__ prho_out, double* __restrict__ pex_out,
                                               double* __restrict__ pth_out) {
@@ -540,10 +541,10 @@ struct BCol {
           // row of half level j, then one step of the down sweep
           double tw;
           if (CORR) {
-            tw = cf.a0 * ptw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(pgw, vert, K1, g.es, ws_up, cur.ws, nx.ws, j, ie, inv_area);
+            tw = cf.a0 * (double)ptw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(pgw, vert, K1, g.es, ws_up, cur.ws, nx.ws, j, ie, inv_area);
           } else {
             tw = col_tw<R>(pgw, vert, K1, g.es, w_up, cur.w, nx.w, j, ie, inv_area);
-            ptw0[(size_t)j * cs + c0] = tw;
+            ptw0[(size_t)j * cs + c0] = (R)tw;
           }
           const double wx = cur.w + dtau * (tw - cpd * cur.zth);
           const double A = -cur.gam * beta_p * (eta * atil_p);

@@ -92,7 +92,7 @@ struct Bufs {
   double *ws, *wtmp;
   R* gw;        // [K+1][es] edge terms of the horizontal advection of w
   R* dvn;       // [K][cs] div vn* (predictor column kernel -> corrector damping)
-  double* tw0;  // [K+1][cs] T_w at the substep start (predictor -> corrector)
+  R* tw0;       // [K+1][cs] T_w at the substep start (predictor -> corrector), formed in R
   // outputs of the corrector
   R* vn_out;
   double *w_out, *rho_out, *ex_out, *th_out;

@@ -46,7 +46,8 @@ struct dc_state {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv, *gw, *dvn;
-  double *wstar, *wtmp, *ttmp, *tw0, *fe, *tau, *diag_part, *diag_out;
+  double *wstar, *wtmp, *ttmp, *fe, *tau, *diag_part, *diag_out;
+  void* tw0;  // [K+1][cs] T_w of the predictor, in the stencil precision
   // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
   // curl L1 of the diffusion front [K][vs], judge and range flags [es],
   // counters (4 int, then one 64-bit)
@@ -106,7 +107,7 @@ Bufs<R> substep_bufs(const dc_state* s, int cur_idx, bool w_to_staging) {
   b.wtmp = s->wtmp;
   b.gw = static_cast<R*>(s->gw);
   b.dvn = static_cast<R*>(s->dvn);
-  b.tw0 = s->tw0;
+  b.tw0 = static_cast<R*>(s->tw0);
   b.vn_out = static_cast<R*>(nxt.vn);
   b.w_out = w_to_staging ? s->wtmp : static_cast<double*>(nxt.w);
   b.rho_out = static_cast<double*>(nxt.rho);
