@@ -39,14 +39,14 @@ def kernel_bytes(C, E, V, K, r):
     return {
         # reads vn; writes vt, K_e (edges), zeta (vertices)
         "vort_ke_pred": r * KE + 2 * r * KE + r * KV,
-        # reads vn, zeta, K_e, vt, w, exner, theta; writes X = a0 T_vn0 - PGF, vn*, gw
+        # reads vn, zeta, K_e, vt, w, exner, theta; writes Y = vn + dtau (a0 T_vn0 - PGF), vn*, gw
         "edge_pred": r * KE + r * KV + 2 * r * KE + 8 * K1C + 8 * 2 * KC + r * 3 * KE,
         # reads gw, vn*, w, rho, exner, theta; writes w*, tw0, D = div vn*
         "column_pred": r * K1E + r * KE + 8 * K1C + 8 * 3 * KC + 8 * K1C + r * K1C + r * KC,
         # reads vn*, D; writes vt, K_e, zeta, D2
         "vort_ke_corr": 3 * r * KE + r * KV + 2 * r * KC,
-        # reads vn*, X = a0 T_vn0 - PGF, vn, zeta, K_e, vt, D2, w*; writes vn', gw
-        "edge_corr": r * 3 * KE + r * KV + 2 * r * KE + r * KC + 8 * K1C + r * 2 * KE,
+        # reads vn*, Y, zeta, K_e, vt, D2, w*; writes vn', gw
+        "edge_corr": r * 2 * KE + r * KV + 2 * r * KE + r * KC + 8 * K1C + r * 2 * KE,
         # reads gw, vn', w, w*, tw0, rho, exner, theta; writes w, rho, exner, theta
         "column_corr": r * K1E + r * KE + 8 * 2 * K1C + r * K1C + 8 * 3 * KC + 8 * (K1C + 3 * KC),
         "diff_vertex": r * KE + r * 4 * KV,

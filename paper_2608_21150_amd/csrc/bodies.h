@@ -175,8 +175,8 @@ struct BVc {
 // ---------------------------------------------------------------------------
 // edge: advective tendency T_vn and the horizontal momentum update.
 //  predictor: vn* = vn + dtau (T_vn - cpd theta_e grad pi')       -> vns, and
-//             X = a0 T_vn - cpd theta_e grad pi' stored in tvn0
-//  corrector: vn' = vn_now + dtau (X + a1 T*) - c4 Abar^2 grad(D2)  -> vn_out
+//             Y = vn + dtau (a0 T_vn - cpd theta_e grad pi')        -> tvn0
+//  corrector: vn' = Y + (dtau a1 T* - c4 Abar^2 grad(D2))          -> vn_out
 // The pressure-gradient term is formed from the state at the start of the
 // substep in both passes.
 // ---------------------------------------------------------------------------
@@ -192,7 +192,6 @@ struct BEdge {
     const double* th;
     R* tvn0;
     R* vout;
-    const R* vn_now;
     const R* d2;
     R* gw;  // out: l_e vn_ie (w_c1 - w_c0) at the half levels 1..K-1
     StepCoef cf;
@@ -210,7 +209,6 @@ struct BEdge {
     const double* __restrict__ th = args.th;
     R* __restrict__ tvn0 = args.tvn0;
     R* __restrict__ vout = args.vout;
-    const R* __restrict__ vn_now = args.vn_now;
     const R* __restrict__ d2 = args.d2;
     const StepCoef cf = args.cf;
     const int kb = args.kb;
@@ -271,20 +269,21 @@ struct BEdge {
       const size_t rc = (size_t)j * g.cs;
       if (!CORR) {
         // the pressure-gradient term comes from the substep's start state in
-        // both passes: the predictor forms it once and stores it with its
-        // share of the tendency, a0 T_vn0 - cpd theta_e grad pi', which is all
-        // the corrector needs of either
+        // both passes: the predictor forms it once and stores the start vn
+        // advanced by it and by its share of the tendency,
+        // vn + dtau (a0 T_vn0 - cpd theta_e grad pi'), which is all the
+        // corrector needs of the three
         const double exr = exref[j];
         const R gex = (R)((ex[rc + c1] - exr) - (ex[rc + c0] - exr)) * invd_r;
         const R the = (R)(0.5 * (th[rc + c0] + th[rc + c1]));
         const R pgf = (R)cf.cpd * the * gex;
         if (in) {
-          tvn0[re] = (R)cf.a0 * tvn - pgf;
+          tvn0[re] = vj + (R)cf.dtau * ((R)cf.a0 * tvn - pgf);
           vout[re] = vj + (R)cf.dtau * (tvn - pgf);
         }
       } else {
         const R dd = (d2[rc + c1] - d2[rc + c0]) * invd_r;
-        if (in) vout[re] = vn_now[re] + (R)cf.dtau * (tvn0[re] + (R)cf.a1 * tvn) - (R)cf.c4a2 * dd;
+        if (in) vout[re] = tvn0[re] + ((R)cf.dtau * (R)cf.a1 * tvn - (R)cf.c4a2 * dd);
       }
       vup = vj;
       vj = vdn;
@@ -1238,10 +1237,10 @@ SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& 
   const int Pp = col_chunks_lm(g.K, false, &lm), Pc = col_chunks_lm(g.K, true, &lm);
   const int neb = cdiv(g.ne, T[T_VC].threads), nvb = cdiv(g.nv, T[T_VC].threads);
   s.vc_p = {b.vn, b.zeta, b.vt, b.kc, nullptr, nullptr, neb, nvb, T[T_VC].kb};
-  s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, nullptr, b.gw, c, T[T_EDGE].kb};
+  s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, b.gw, c, T[T_EDGE].kb};
   s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr}, c, Pp};
   s.vc_c = {b.vns, b.zeta, b.vt, b.kc, b.d2, b.dvn, neb, nvb, T[T_VC].kb};
-  s.e_c = {b.vns, b.zeta, b.kc, b.vt, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.vn, b.d2, b.gw, c, T[T_EDGE].kb};
+  s.e_c = {b.vns, b.zeta, b.kc, b.vt, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.d2, b.gw, c, T[T_EDGE].kb};
   s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, Pc};
   return s;
 }
