@@ -392,6 +392,8 @@ def main():
     ap.add_argument("--no-theta", action="store_true", help="skip the run with the theta_v diffusion on")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--stream-probe", type=int, default=0, metavar="MIB",
+                    help="only time plain streams over MIB MiB (read, write, copy; torch kernels) and exit")
     ap.add_argument("--summarize-profile", nargs=5, metavar=("TRACE", "FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write a profile summary from rocprofv3 output folders and exit")
     ap.add_argument("--profile-out", default=None)
@@ -417,6 +419,28 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
+
+    if args.stream_probe:
+        # what plain streaming reaches on this GPU: the practical side of the
+        # HBM roofline (best of 5 after a warm-up, events on the current stream)
+        n = args.stream_probe * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        res = {}
+        for name, fn, moved in (("read (sum)", lambda: x.sum(), n * 8), ("write (fill)", lambda: y.fill_(2.0), n * 8),
+                                ("copy", lambda: y.copy_(x), 2 * n * 8)):
+            fn()
+            best = 1e30
+            for _ in range(5):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                torch.cuda.synchronize()
+                best = min(best, a.elapsed_time(b))
+            res[name] = {"ms": round(best, 4), "GB/s": round(moved / best / 1e6, 1)}
+        print(json.dumps({"stream_probe_bytes": n * 8, "results": res}))
         return
 
     from paper_2608_21150_amd import dycore as D
