@@ -132,3 +132,29 @@ def test_cell_and_edge_means(g2):
     e = np.full((1, g2.ne), 5.0)
     assert np.all(op.avg_e(g2, c) == 3.0)
     assert np.all(op.avg_c(g2, e) == 5.0)
+
+
+def test_scalar_laplacian_spherical_harmonics():
+    """Closed form: on the sphere of radius R a spherical harmonic of degree l
+    is an eigenfunction of the Laplacian, lap Y = -l(l+1)/R^2 Y.  The cell
+    Laplacian (two-point fluxes l_e/d_e across triangle edges) converges to
+    it in the area-weighted L2 norm, about half an order per bisection on
+    these grids (pointwise it keeps an O(1) error at irregular cells, as
+    such triangle-based Laplacians do), and its Rayleigh quotient gives the
+    eigenvalue to within 2 % from R2B4 on: a swapped l_e/d_e, a lost area or a
+    flipped sign fails by far."""
+    zh, zf = vertical(1, 10e3)
+    errs = {1: [], 2: [], 3: []}
+    for k in (2, 3, 4):
+        g = Grid(make_grid(2, k), {"z_half": zh, **reference(zh, zf)})
+        x = g.xc / np.linalg.norm(g.xc, axis=1, keepdims=True)
+        for l, phi in ((1, x[:, 2]), (2, x[:, 0] * x[:, 1]), (3, x[:, 2] * (5 * x[:, 2] ** 2 - 3))):
+            lap = op.laps(g, phi[None])[0]
+            lam = -l * (l + 1) / g.radius**2
+            errs[l].append(np.sqrt(np.sum(g.a_c * (lap - lam * phi) ** 2) / np.sum(g.a_c * (lam * phi) ** 2)))
+            if k == 4:
+                rq = np.sum(g.a_c * phi * lap) / np.sum(g.a_c * phi * phi)
+                assert abs(rq / lam - 1) < 0.02, (l, rq / lam)
+    for l, e in errs.items():
+        assert e[0] > e[1] > e[2], (l, e)
+        assert e[2] < 0.03, (l, e)
