@@ -120,6 +120,14 @@ def test_validation_errors(grids):
     _expect(D.DC_EGRID, bad(n_verts=g["n_verts"] + 1,
                             vert_xyz=np.vstack([g["vert_xyz"], [[0, 0, 1]]]),
                             dual_area=np.append(g["dual_area"], 1.0)))
+    # the column solver's depth limit: 129 levels accepted, 130 refused
+    _, v129 = initial_state(g, 129, 60e3, seed=0)
+    D.Grid(g, v129).close()
+    _, v130 = initial_state(g, 130, 60e3, seed=0)
+    _expect(D.DC_EINVAL, lambda: D.Grid(g, v130))
+    xc = g["cell_xyz"].copy()
+    xc[4, 1] = np.nan
+    _expect(D.DC_EGRID, bad(cell_xyz=xc))
     # NULL description and NULL output
     assert D.lib.dc_grid_create(None, None) == D.DC_EINVAL
     assert D.lib.dc_params_default(None) == D.DC_EINVAL
