@@ -51,7 +51,7 @@ def run_oracle(g0, vert, S, dt, nsub, steps, diffuse=True):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def r2b2_case():
     g0, S, vert, spec = build_workload("r2b2_k30")
     ref, og = run_oracle(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"])
     return g0, S, vert, spec, ref, og
@@ -66,8 +66,8 @@ def test_rest_state_stays_at_rest():
 
 
 @pytest.mark.parametrize("sfc", [False, True])
-def test_config1_parity_10_steps(cfg1, sfc):
-    g0, S, vert, spec, ref, _ = cfg1
+def test_r2b2_parity_10_steps(r2b2_case, sfc):
+    g0, S, vert, spec, ref, _ = r2b2_case
     out, _ = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], spec["steps"], sfc=sfc)
     errs = {k: rel_l2(out[k], ref[k]) for k in FIELDS}
     print("rel L2 vs oracle:", errs)
@@ -112,8 +112,8 @@ def test_deep_columns_every_chunk_length(n_lev):
         assert rel_l2(out[k], ref[k]) <= 1e-11, (n_lev, k, rel_l2(out[k], ref[k]))
 
 
-def test_conservation_diagnostics(cfg1):
-    g0, S, vert, spec, ref, og = cfg1
+def test_conservation_diagnostics(r2b2_case):
+    g0, S, vert, spec, ref, og = r2b2_case
     G = D.Grid(g0, vert)
     st = D.State(G)
     st.write(S)
@@ -253,7 +253,7 @@ def test_theta_diffusion_parity_and_batching():
 
 def test_near_surface_enhancement_parity():
     """The near-surface floor on the theta_v coefficient with the theta_v
-    diffusion: config 1's state with 40 cold pools (12 K colder in the three
+    diffusion: the R2B2 / 30-level state with 40 cold pools (12 K colder in the three
     lowest levels, pressure unchanged) so that the floor acts; three steps
     with the floor in the four lowest levels, FP64 against the oracle with
     the same options; the floor changes the result; mixed precision stays

@@ -2,7 +2,7 @@
 Section 4.4): tolerances come from the spread that tiny perturbations of the
 initial state grow to, not from a fixed threshold.
 
-Config 1 (R2B2, 30 levels, 10 steps of 600 s, 5 substeps).  Seven members
+The R2B2 / 30-level workload (10 steps of 600 s, 5 substeps).  Seven members
 perturb theta_v by a relative amount eps (seeded, uniform in [-eps, eps]); the
 members run together through the ensemble runner (one graph launch per
 step).  The tolerance of a field is FACTOR times the largest relative L2
@@ -40,7 +40,7 @@ def rel(a, b):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def r2b2_case():
     g0, S, vert, spec = build_workload("r2b2_k30")
     G = D.Grid(g0, vert)
     yield g0, S, vert, spec, G
@@ -75,8 +75,8 @@ def tolerances(G, S, spec, eps):
     return out[0], {f: FACTOR * v for f, v in spread.items()}
 
 
-def test_gpu_fp64_within_rounding_ensemble_spread_of_oracle(cfg1):
-    g0, S, vert, spec, G = cfg1
+def test_gpu_fp64_within_rounding_ensemble_spread_of_oracle(r2b2_case):
+    g0, S, vert, spec, G = r2b2_case
     gpu, tol = tolerances(G, S, spec, 1e-14)
     og = OGrid(g0, vert)
     wts = O.vertex_lsq_weights(og)
@@ -90,8 +90,8 @@ def test_gpu_fp64_within_rounding_ensemble_spread_of_oracle(cfg1):
         assert err[f] <= tol[f], (f, err[f], tol[f])
 
 
-def test_mixed_within_1e8_ensemble_spread_of_fp64(cfg1):
-    g0, S, vert, spec, G = cfg1
+def test_mixed_within_1e8_ensemble_spread_of_fp64(r2b2_case):
+    g0, S, vert, spec, G = r2b2_case
     fp64, tol = tolerances(G, S, spec, 1e-8)
     mixed = run(G, [S], spec, precision="mixed")[0]
     err = {f: rel(mixed[f], fp64[f]) for f in FIELDS}

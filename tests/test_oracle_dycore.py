@@ -24,7 +24,7 @@ from synth import build_workload, initial_state, make_grid
 
 
 @pytest.fixture(scope="module")
-def cfg1():
+def r2b2_case():
     g0, S, vert, spec = build_workload("r2b2_k30")
     return Grid(g0, vert), S, spec
 
@@ -34,8 +34,8 @@ def r2b3():
     return make_grid(2, 3)
 
 
-def test_rest_state_bitwise(cfg1):
-    g, _, spec = cfg1
+def test_rest_state_bitwise(r2b2_case):
+    g, _, spec = r2b2_case
     g0, S, vert, _ = build_workload("r2b2_k30_rest")
     S1 = S
     for _ in range(10):
@@ -44,8 +44,8 @@ def test_rest_state_bitwise(cfg1):
         assert np.array_equal(S1[k], S[k]), k
 
 
-def test_mass_conservation(cfg1):
-    g, S, spec = cfg1
+def test_mass_conservation(r2b2_case):
+    g, S, spec = r2b2_case
     m0 = dycore.diag(g, S)["mass"]
     S1 = S
     for _ in range(10):
