@@ -11,8 +11,8 @@ substeps starting with the advective tendencies, horizontal momentum update,
 divergence damping only in the corrector, vertically implicit solver, and a
 diffusion granule called once per time step; Section 5.1 "Experimental setup"
 for the nh_solve / nh_diff split and the icosahedral grid).  The paper prints
-no equations; every numerical detail is a written-out reading listed in
-DESIGN.md ("Readings of the paper").
+no equations; every numerical detail is a written-out reading, stated in
+the docstring of the function that implements it.
 
 Modules:
   constants  -- physical constants and scheme parameters

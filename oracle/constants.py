@@ -3,7 +3,7 @@
 The paper defers the discretisation to ICON's published one and prints no
 constants; these are the documented ICON values for a dry atmosphere
 (Earth radius 6.371e6 m as the workloads state) and the scheme constants of
-the readings listed in the design doc.
+the readings, each commented below.
 """
 
 RD = 287.04          # gas constant of dry air [J/kg/K]

@@ -8,7 +8,7 @@ advective tendencies, updates the horizontal momentum with pressure gradient
 and advection, and advances w and the thermodynamic state with a vertically
 implicit column solver; divergence damping is applied in the corrector only.
 Diffusion is Smagorinsky plus fourth-order background on vn, second order on
-w.  The discretisation of each step is a reading (DESIGN.md, "Readings");
+w.  The discretisation of each step is a reading, stated where it is coded;
 symbols follow the usual non-hydrostatic ICON notation:
 
   state      vn [K][E], w [K+1][C], rho, exner, theta_v [K][C]

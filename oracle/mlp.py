@@ -2,7 +2,7 @@
 
 The paper motivates a modular Python dynamical core with integration of
 machine-learning workflows (Section 3, Section 6); the surrogate itself is a
-reading: an 18 -> 64 -> 64 -> 1 multilayer perceptron with exact
+reading of this project: an 18 -> 64 -> 64 -> 1 multilayer perceptron with exact
 (erf) GELU, predicting the vn tendency of the diffusion step from stencil
 features of one (edge, level).
 
