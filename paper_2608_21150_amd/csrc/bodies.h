@@ -7,7 +7,11 @@
 // once per thread and every level access of the own entity is a coalesced
 // 64-wide row.  Gathers go through the lookup tables (paper, Section 4.2.1).
 // Single-state launches remap blocks so that the 8 XCDs each sweep a
-// contiguous range of tiles (neighbour halos then mostly hit one XCD's L2).
+// contiguous range of tiles (neighbour halos then mostly hit one XCD's L2);
+// bodies with kXcdRanges = false keep the hardware's round-robin order
+// instead (the vorticity, edge and cell-vertex diffusion passes, whose edge
+// and vertex tiles read the same rows and run faster when every XCD works
+// on every part of the grid at once).
 //
 // Template parameter R is the type of vn and of the horizontal-stencil
 // intermediates: double for the FP64 path, float for the mixed path.  The
@@ -23,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernels.h"
@@ -89,6 +94,7 @@ struct BVc {
     int neb, nvb;
     int kb;
   };
+  static constexpr bool kXcdRanges = false;  // round-robin tile order (see the top of this file)
   static constexpr int kThreads = 256;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const R* __restrict__ vn = args.vn;
@@ -197,6 +203,7 @@ struct BEdge {
     StepCoef cf;
     int kb;
   };
+  static constexpr bool kXcdRanges = false;  // round-robin tile order (see the top of this file)
   static constexpr int kThreads = 256;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const R* __restrict__ vn = args.vn;
@@ -1000,6 +1007,7 @@ struct BDcv2 {
     StepCoef cf;
     int kb;
   };
+  static constexpr bool kXcdRanges = false;  // round-robin tile order (see the top of this file)
   static constexpr int kThreads = 256;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const R* __restrict__ l1 = args.l1;
@@ -1127,10 +1135,20 @@ struct BDedge2 {
 // launch wrappers
 // ---------------------------------------------------------------------------
 // one state: 2-D grid of tiles, XCD-aware order
+template <typename B, typename = void>
+struct xcd_ranges : std::true_type {};
+template <typename B>
+struct xcd_ranges<B, std::void_t<decltype(B::kXcdRanges)>> : std::bool_constant<B::kXcdRanges> {};
+
 template <typename B>
 __global__ void __launch_bounds__(B::kThreads) k_one(DevGrid g, typename B::Args a) {
   int bx, by;
-  tile_coords(bx, by);
+  if constexpr (xcd_ranges<B>::value) {
+    tile_coords(bx, by);
+  } else {
+    bx = blockIdx.x;
+    by = blockIdx.y;
+  }
   B::run(g, a, bx, by);
 }
 
