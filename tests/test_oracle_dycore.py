@@ -11,7 +11,15 @@ Each pin targets a part of the step where a plausible slip would show:
     buoyancy and vertical pressure-gradient signs);
   * vertical advection signs, diffusion and divergence damping dissipate,
     Smagorinsky sees no deformation in rigid rotation, the least-squares
-    vertex vector is exact for a uniform tangent vector.
+    vertex vector is exact for a uniform tangent vector;
+  * theta-mass conserved to round-off, and the column update keeps the
+    equation of state to second order in the pressure increment (theta_v
+    increment);
+  * the sponge profile's zeros, top value, midpoint and layer mean;
+  * the horizontal advection of w converges to -u . grad w for a
+    solid-body rotation;
+  * the w diffusion: uniform levels untouched, the capped-viscosity
+    increment of a degree-1 harmonic in closed form, energy not growing.
 """
 import numpy as np
 import pytest
@@ -280,3 +288,188 @@ def test_near_surface_enhancement_ramp_and_band(r2b3):
     # a larger threshold moves the ramp: dT = 3 T with threshold 2 T gives s = 0.5
     half = _cold_pool_increment(g, S, c, K - 1, -3.0 * T, 1, {"theta_enh_thresh": 2.0 * T})[0]
     assert abs(half / inc[3.0] - 0.5) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# pins of the theta_v increment, the sponge profile, the horizontal advection
+# of w and the w diffusion (each fails under the slip named in its docstring)
+# ----------------------------------------------------------------------------
+def test_theta_mass_conserved(r2b2_case):
+    """The increment form of the column update (Section 4.1, vertically
+    implicit solver) changes rho theta_v by the divergence of the theta flux
+    only: rho* theta_v* = rho theta_v (1 + (c_vd/R_d) d_pi/pi), and
+    (c_vd/R_d) rho theta_v b / pi = dtau.  So the total theta-mass telescopes
+    like the mass.  An inverted c_vd/R_d, or a theta_v update that drops the
+    -theta_v d_rho term, breaks it at first order."""
+    g, S, spec = r2b2_case
+    t0 = dycore.diag(g, S)["theta_mass"]
+    S1 = S
+    for _ in range(10):
+        S1 = dycore.step(g, S1, spec["dt"], spec["nsub"])
+    assert abs(dycore.diag(g, S1)["theta_mass"] / t0 - 1.0) <= 1e-13
+
+
+def test_column_update_keeps_equation_of_state_to_second_order(r2b3):
+    """Exner is advanced by the equation of state linearised in the pressure
+    increment (Section 4.1; the linearised form of the Exner equation).  With
+    x = d_pi / pi and a = c_vd / R_d, the update gives pi* = pi (1 + x) and
+    rho* theta_v* = rho theta_v (1 + a x), so the full equation of state
+    pi(rho theta_v) = (R_d rho theta_v / p0)^(1/a) differs from pi* by
+    pi ((1 + x) - (1 + a x)^(1/a)) = pi (a - 1) x^2 / 2 + O(x^3) at every
+    point.  Any first-order slip in the rho, exner or theta_v increments
+    (a wrong c_vd/R_d, a lost theta_v d_rho term) leaves a residual of order x."""
+    S, vert = initial_state(r2b3, 20, 30e3, seed=3, jet_u0=35.0, n_bumps=10, bump_amp=3.0,
+                            bump_radius=1000e3, vn_sigma=2.0)
+    g = Grid(r2b3, vert)
+    p = default_params()
+    a = p["cvd"] / p["rd"]
+    # the initial state satisfies the equation of state to round-off
+    eos0 = (p["rd"] * S["rho"] * S["theta_v"] / 1.0e5) ** (1.0 / a)
+    assert np.max(np.abs(eos0 / S["exner"] - 1.0)) < 1e-14
+    for dtau in (40.0, 10.0):
+        pred, _ = dycore.predictor(g, p, S, dtau)
+        x = pred["exner"] / S["exner"] - 1.0
+        eos = (p["rd"] * pred["rho"] * pred["theta_v"] / 1.0e5) ** (1.0 / a)
+        resid = pred["exner"] - eos
+        lead = S["exner"] * (a - 1.0) * x * x / 2.0
+        m = np.abs(x) > 1e-5
+        assert m.sum() > 1000
+        ratio = resid[m] / lead[m]
+        assert np.max(np.abs(ratio - 1.0)) < 2e-3, (dtau, ratio.min(), ratio.max())
+        # and nowhere a first-order residual
+        assert np.max(np.abs(resid)) <= 1.01 * np.max(np.abs(lead)) + 1e-15
+
+
+def test_sponge_profile():
+    """Rayleigh damping (the upper sponge of the column solver): zero at and
+    below z_d = 2/3 z_top, tau0 at the model top, tau0/2 halfway between
+    (sin^2(pi/4) = 1/2), and a layer mean of tau0/2 (the mean of sin^2 over a
+    quarter period).  A sin profile instead of sin^2 gives 0.71 and 0.64;
+    a wrong z_d moves the zeros."""
+    g0 = make_grid(1, 0)
+    K = 300
+    _, vert = initial_state(g0, K, 30e3, seed=0)
+    g = Grid(g0, vert)
+    p = default_params()
+    tau0 = p["rayleigh_tau0"]
+    tau = dycore.rayleigh_tau(g, p)
+    z = g.z_half
+    z_d = 20e3
+    assert np.all(tau[z <= z_d + 1e-6] == 0.0)
+    assert np.all(tau[z > z_d + 1e-6] > 0.0)
+    assert tau[0] == tau0  # model top
+    mid = np.argmin(np.abs(z - 25e3))
+    assert abs(z[mid] - 25e3) < 1e-6
+    assert abs(tau[mid] / tau0 - 0.5) < 1e-12
+    # layer mean over [z_d, z_top] by the trapezoid rule on the half levels
+    band = z >= z_d - 1e-6
+    zz, tt = z[band][::-1], tau[band][::-1]
+    mean = np.sum(0.5 * (tt[1:] + tt[:-1]) * np.diff(zz)) / (zz[-1] - zz[0])
+    assert abs(mean / tau0 - 0.5) < 1e-4
+    # the solver divides w* by (1 + dtau tau): a resting column with w only
+    # at the top half level loses it at that rate, compare the damped and
+    # undamped columns' w after one predictor
+    S, vert = initial_state(g0, 30, 30e3, seed=0)
+    g30 = Grid(g0, vert)
+    S = dict(S)
+    S["w"] = S["w"].copy()
+    S["w"][1] = 0.1
+    p0 = dict(p)
+    p0["rayleigh_tau0"] = 0.0
+    dtau = 10.0
+    w_damped = dycore.predictor(g30, p, S, dtau)[0]["w"]
+    w_free = dycore.predictor(g30, p0, S, dtau)[0]["w"]
+    tau30 = dycore.rayleigh_tau(g30, p)
+    assert np.allclose(w_damped[1:30], w_free[1:30] / (1.0 + dtau * tau30[1:30, None]), rtol=1e-14, atol=0.0)
+
+
+def _solid_body_vn(g, axis, omega, n_lev):
+    u = omega * g.radius * np.cross(np.asarray(axis, dtype=float), g.xe)
+    return np.repeat(np.einsum("ej,ej->e", u, g.nrm)[None], n_lev, axis=0)
+
+
+def test_horizontal_w_advection_converges_to_closed_form():
+    """Horizontal part of the vertical-wind advection (velocity advection,
+    Section 4.1).  For a solid-body rotation about the x axis,
+    u = omega R (x_hat x r_hat), and w = W sin(lat) = W z_hat . r_hat, the
+    continuous term is -u . grad w = -omega W y.  With w uniform in the
+    vertical the vertical part vanishes, so T_w is the horizontal part
+    alone; its relative RMS error against -omega W y_c must fall with every
+    refinement R2B2 -> R2B5.  A lost factor 1/2 or a flipped sign leaves an
+    error of 1 or 2."""
+    errs = []
+    om, W, K = 1e-5, 2.0, 3
+    for k in (2, 3, 4, 5):
+        g0 = make_grid(2, k)
+        _, vert = initial_state(g0, K, 10e3, seed=0)
+        g = Grid(g0, vert)
+        vn = _solid_body_vn(g, (1.0, 0.0, 0.0), om, K)
+        w = np.repeat((W * g.xc[:, 2])[None], K + 1, axis=0)
+        _, t_w = dycore.velocity_advection(g, default_params(), vn, w)
+        exact = -om * W * g.xc[:, 1]
+        for j in range(1, K):
+            assert np.array_equal(t_w[j], t_w[1])
+        errs.append(np.sqrt(np.mean((t_w[1] - exact) ** 2) / np.mean(exact**2)))
+    assert errs[0] < 0.1
+    for a, b in zip(errs[:-1], errs[1:]):
+        assert b < 0.8 * a, errs
+    assert errs[-1] < 0.025, errs
+
+
+def test_w_diffusion_pins():
+    """Second-order Smagorinsky diffusion of w (the diffusion granule,
+    Section 4.1): w(k) += dt nu_c(k) laps(w)(k) with nu_c the cell mean of
+    nu at half levels.  Pins:
+      * a horizontally uniform w is left bitwise unchanged (laps of a
+        constant is exactly zero), and so are the boundaries w(0), w(K);
+      * with nu on its stability cap A_e / (16 dt) at one full level j and
+        zero elsewhere, only half levels j and j+1 move, by the same amount,
+        and for w = W sin(lat) (a degree-1 harmonic, laps = -2 w / R^2) the
+        increment is -(mean_e A_e) / (16 R^2) w: the half-level mean (1/2),
+        the cell mean (1/3), dt and the sign are all fixed by this value;
+      * sum A_c w^2 does not grow for a random w under a random flow."""
+    g0 = make_grid(2, 3)
+    K = 5
+    S, vert = initial_state(g0, K, 10e3, seed=0)
+    g = Grid(g0, vert)
+    p = default_params()
+    dt = 600.0
+    rng = np.random.default_rng(1)
+    S2 = dict(S)
+    S2["vn"] = rng.normal(0.0, 20.0, (K, g.ne))
+    S2["w"] = np.zeros((K + 1, g.nc))
+    S2["w"][1:K] = rng.normal(0.0, 1.0, (K - 1, 1))  # uniform on every half level
+    out = dycore.diffusion(g, p, S2, dt)
+    assert np.array_equal(out["w"], S2["w"])
+    # capped viscosity at full level 1 only (not the middle one, so that a
+    # level mix-up shows)
+    p_cap = dict(p)
+    p_cap["smag_cs"] = 1e9
+    W = 3.0
+    S3 = dict(S)
+    S3["vn"] = np.zeros((K, g.ne))
+    S3["vn"][1] = rng.normal(0.0, 1.0, g.ne)
+    S3["w"] = np.zeros((K + 1, g.nc))
+    S3["w"][1:K] = W * g.xc[:, 2][None]
+    S3["w"][0] = S3["w"][K] = 1.0  # boundary values must stay as they are
+    out = dycore.diffusion(g, p_cap, S3, dt)
+    inc = out["w"] - S3["w"]
+    for k in (0, 3, 4, 5):
+        assert np.all(inc[k] == 0.0), k
+    assert np.array_equal(inc[1], inc[2])
+    ae_c = (g.a_e[g.c2e[:, 0]] + g.a_e[g.c2e[:, 1]] + g.a_e[g.c2e[:, 2]]) / 3.0
+    exact = -ae_c / (16.0 * g.radius**2) * W * g.xc[:, 2]
+    rms = np.sqrt(np.mean((inc[1] - exact) ** 2) / np.mean(exact**2))
+    assert rms < 0.04, rms
+    big = np.abs(exact) > 0.1 * np.abs(exact).max()
+    assert abs(np.median(inc[1][big] / exact[big]) - 1.0) < 0.01
+    # energy of a random w under a random flow
+    S4 = dict(S)
+    S4["vn"] = rng.normal(0.0, 20.0, (K, g.ne))
+    S4["w"] = np.zeros((K + 1, g.nc))
+    S4["w"][1:K] = rng.normal(0.0, 1.0, (K - 1, g.nc))
+    out = dycore.diffusion(g, p, S4, dt)
+    e0 = np.sum(g.a_c * S4["w"] ** 2)
+    e1 = np.sum(g.a_c * out["w"] ** 2)
+    assert e1 < e0
+    assert np.abs(out["w"] - S4["w"]).max() > 1e-6  # it did act
