@@ -1,10 +1,18 @@
 """Throughput of the dycore time step on one MI355X (plus the oracle on the host).
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload r2b5_k65]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload r2b8_k90]
 
 A step is one dc_dycore_step: nsub predictor-corrector substeps and one
 diffusion step over the whole grid.  Inputs are resident in HBM when the
 timed region starts.  Prints one JSON line (rank 0, N = 1).
+
+The default workload is the largest single-GPU one: R2B8 (5,242,880 cells,
+7,864,320 edges), 90 levels, curve-ordered, dt 30 s, 5 substeps, FP64, with
+the mixed form measured beside it on the same steps.  The R2B5 / 65-level
+jet workload follows as a secondary block: its rate, and the error of the
+mixed form against FP64 per field after its 100 steps.  The oracle is timed
+on one host core on a sample of the R2B5 workload (an R2B8 step is out of the
+host's reach).
 
 Sequence per precision: dc_state_autotune (launch tiles; fields restored),
 W warm-up steps, K steps with events around every launch (the per-kernel
@@ -58,15 +66,45 @@ def kernel_bytes(C, E, V, K, r):
 
 
 def step_algorithmic_bytes(C, E, K, nsub, r):
-    """Compulsory HBM traffic of a whole step with perfect fusion: each
-    substep reads the state once for the predictor and once (plus the
-    predicted vn, w) for the corrector and writes the new state; diffusion
-    reads and writes vn and w once."""
+    """Compulsory HBM traffic of a whole step with perfect fusion, as the
+    scope table's measurement section counts it: each substep's predictor
+    reads the state S^n and writes the predicted state S* (all five fields),
+    the corrector reads S^n and the predicted vn*, w* and writes S^{n+1};
+    diffusion reads and writes vn and w once.  FP64 (r = 8): 1,020 B per
+    cell and level at nsub = 5 with E = 1.5 C; mixed (vn in FP32): 858 B."""
     state = r * K * E + 8 * ((K + 1) * C + 3 * K * C)
-    pred = state + r * K * E + 8 * (K + 1) * C            # read S^n, write vn*, w*
+    pred = 2 * state                                       # read S^n, write S*
     corr = state + r * K * E + 8 * (K + 1) * C + state    # read S^n, vn*, w*, write S^{n+1}
     diff = 2 * (r * K * E + 8 * (K + 1) * C)
     return nsub * (pred + corr) + diff
+
+
+def step_algorithmic_bytes_r15(C, E, K, nsub, r):
+    """The same with the predictor writing only vn* and w*: the corrector
+    reuses the predictor's pressure gradient and column coefficients, all of
+    which depend on S^n only, so the predicted rho, exner, theta_v are never
+    needed (903 B per cell and level in FP64)."""
+    state = r * K * E + 8 * ((K + 1) * C + 3 * K * C)
+    pred = state + r * K * E + 8 * (K + 1) * C
+    corr = state + r * K * E + 8 * (K + 1) * C + state
+    diff = 2 * (r * K * E + 8 * (K + 1) * C)
+    return nsub * (pred + corr) + diff
+
+
+def kernel_compulsory_bytes(kid, C, E, K, r):
+    """A column kernel's share of the compulsory traffic (the per-phase words
+    of the scope table's measurement section): column_corr reads w, rho,
+    exner, theta_v of S^n, the predicted w* and the new vn whose fluxes it
+    forms, and writes w, rho, exner, theta_v of S^{n+1}; column_pred reads
+    S^n's w, rho, exner, theta_v and vn*, and writes w*.  None for kernels
+    without a natural share (the horizontal passes split the edge fields
+    between them)."""
+    cells = 8 * ((K + 1) * C + 3 * K * C)
+    if kid == "column_corr":
+        return 2 * cells + 8 * (K + 1) * C + r * K * E
+    if kid == "column_pred":
+        return cells + r * K * E + 8 * (K + 1) * C
+    return None
 
 
 # kernels of the step as rocprofv3 names them -> the ids used above
@@ -208,6 +246,64 @@ def cpu_baseline(spec, g0, S, vert, budget_s=25.0):
                       f"{os.cpu_count()}"}
 
 
+def bench_r2b5(args, D, torch, dev):
+    """The R2B5 / 65-level jet workload (81,920 cells, dt 180 s, 5
+    substeps): FP64 and mixed rates (tuned tiles, warm-up, timed steps), and
+    the mixed form's error against FP64 per field after the workload's 100
+    steps from the same initial state, with the mass drift of both."""
+    import numpy as np
+
+    from synth import build_workload
+
+    name = "r2b5_k65"
+    print(f"[bench] secondary workload {name}", file=sys.stderr, flush=True)
+    g0, S, vert, spec = build_workload(name)
+    C, K = g0["n_cells"], spec["n_lev"]
+    G = D.Grid(g0, vert, sfc=bool(spec.get("sfc", 0)))
+    stream = torch.cuda.current_stream(dev)
+    res = {"workload": f"{name}: R2B5 icosahedral grid, {C} cells, {K} levels, dt {spec['dt']} s, "
+                       f"{spec['nsub']} substeps, generator-ordered"}
+    for prec in ("fp64", "mixed"):
+        st = D.State(G, precision=prec, device=dev)
+        st.write(S)
+        if not args.no_autotune:
+            st.autotune(spec["dt"], spec["nsub"])
+        for _ in range(args.warmup):
+            st.step(spec["dt"], spec["nsub"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            st.step(spec["dt"], spec["nsub"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        st.close()
+        b = step_algorithmic_bytes(C, g0["n_edges"], K, spec["nsub"], 8 if prec == "fp64" else 4)
+        res[prec] = {"value": C * K / (ms * 1e-3), "ms_per_step": ms,
+                     "step_hbm_effective_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    # errors after the workload's steps, both runs from the initial state
+    outs, diags = {}, {}
+    for prec in ("fp64", "mixed"):
+        st = D.State(G, precision=prec, device=dev)
+        st.write(S)
+        d0 = st.diag()
+        for _ in range(spec["steps"]):
+            st.step(spec["dt"], spec["nsub"])
+        outs[prec], d1 = st.read(), st.diag()
+        diags[prec] = {"mass_rel_drift": d1["mass"] / d0["mass"] - 1.0,
+                       "theta_mass_rel_drift": d1["theta_mass"] / d0["theta_mass"] - 1.0,
+                       "n_nonfinite": d1["n_nonfinite"]}
+        st.close()
+    G.close()
+    res["mixed_rel_l2_vs_fp64"] = {k: float(np.linalg.norm(outs["mixed"][k] - outs["fp64"][k])
+                                         / np.linalg.norm(outs["fp64"][k])) for k in FIELDS}
+    res["after_steps"] = spec["steps"]
+    res["diag"] = diags
+    return res
+
+
 def bench_ensemble(args, D, torch):
     """24 uneven members (12 x R2B4 + 12 x R2B5, 65 levels, mixed precision):
     one graph launch per step against a loop of per-member steps."""
@@ -235,6 +331,27 @@ def bench_ensemble(args, D, torch):
     tune_s = time.perf_counter() - t0
     sched = E.schedule()
     stream = torch.cuda.current_stream()
+    # every member of the batched run equals its run alone: two steps of the
+    # ensemble against solo states of four members (two of each grid)
+    import numpy as np
+
+    for _ in range(2):
+        E.step(dt, nsub)
+    check = (0, 11, 12, 23)
+    member_equal = True
+    for m in check:
+        sp = ensemble_member(m)
+        g, G = grids[sp["k"]]
+        S, _ = initial_state(g, sp["n_lev"], sp["z_top"], **sp["state"])
+        solo = D.State(G, precision="mixed")
+        solo.write(S)
+        for _ in range(2):
+            solo.step(dt, nsub)
+        a, b = states[m].read(), solo.read()
+        solo.close()
+        member_equal &= all(np.array_equal(a[f], b[f]) for f in FIELDS)
+    print(f"[bench] ensemble members {check} bitwise equal to their solo runs: {member_equal}", file=sys.stderr,
+          flush=True)
 
     def timed(fn, steps):
         for _ in range(args.warmup):
@@ -264,6 +381,7 @@ def bench_ensemble(args, D, torch):
                        "members": 24, "cell_levels": cells},
             "per_member_loop": {"ms_per_step": ms_loop, "value": cells / (ms_loop * 1e-3)},
             "speedup_vs_loop": ms_loop / ms_graph, "schedule": sched,
+            "members_bitwise_equal_solo": {"members": list(check), "after_steps": 2, "equal": bool(member_equal)},
             "autotune_s": tune_s}
     for st in states:
         st.close()
@@ -380,7 +498,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="r2b5_k65")
+    ap.add_argument("--workload", default="r2b8_k90")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--sfc", type=int, default=-1, help="1/0 force the space-filling-curve renumbering; -1 workload default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -389,7 +507,9 @@ def main():
     ap.add_argument("--eval-steps", type=int, default=500, help="surrogate: steps of every evaluation run")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch tiles")
-    ap.add_argument("--no-theta", action="store_true", help="skip the run with the theta_v diffusion on")
+    ap.add_argument("--theta", action="store_true", help="also time the step with the theta_v diffusion on")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the R2B5 block (rate and mixed-vs-FP64 errors after 100 steps)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--stream-probe", type=int, default=0, metavar="MIB",
@@ -454,6 +574,7 @@ def main():
     sfc = bool(spec.get("sfc", 0)) if args.sfc < 0 else bool(args.sfc)
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
     g0, S, vert, spec = build_workload(args.workload)
+    S0 = S
     C, E, V, K = g0["n_cells"], g0["n_edges"], g0["n_verts"], spec["n_lev"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -518,12 +639,19 @@ def main():
     dom = R1["dom"]
     calls, tot = R1["dom_timed"]
     avg_ms = tot / calls
-    achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
+    # algorithmic bytes of the dominant kernel: its share of the compulsory
+    # traffic where it has one, else every array it reads or writes once
+    comp = kernel_compulsory_bytes(dom, C, E, K, r)
+    alg_bytes = comp if comp is not None else kb[dom]
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": profiled_traffic(args.workload, args.precision, dom),
-            "bytes_per_launch": kb[dom], "avg_launch_us": round(avg_ms * 1e3, 2),
-            "launches_timed": calls}
+            "bytes_per_launch": alg_bytes,
+            "bytes_basis": "compulsory share" if comp is not None else "kernel arrays",
+            "kernel_arrays_bytes_per_launch": kb[dom],
+            "kernel_arrays_GBps": round(kb[dom] / (avg_ms * 1e-3) / 1e9, 1),
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches_timed": calls}
     b_step = step_algorithmic_bytes(C, E, K, spec["nsub"], r)
     line = {
         "metric": METRIC, "value": value, "unit": "cell·level·steps/s", "n_gpus": 1,
@@ -538,7 +666,9 @@ def main():
                    "autotune_s": None if R1["tune_s"] is None else round(R1["tune_s"], 2)},
         "roofline": roof,
         "step_hbm_effective_frac": round(b_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "step_algorithmic_bytes_per_cell_level": b_step / (C * K),
+        "step_algorithmic_bytes_per_cell_level": round(b_step / (C * K), 1),
+        "step_hbm_effective_frac_predictor_vn_w_only": round(
+            step_algorithmic_bytes_r15(C, E, K, spec["nsub"], r) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": {n: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
                     for n, d in kernels.items()},
         "diag": {"mass": diag["mass"], "n_nonfinite": diag["n_nonfinite"]},
@@ -548,13 +678,15 @@ def main():
         R2 = run("mixed", args.steps, args.warmup, tune)
         ms2, out2, d2 = R2["ms"], R2["out"], R2["diag"]
         errs = {k: float(np.linalg.norm(out2[k] - out[k]) / np.linalg.norm(out[k])) for k in FIELDS}
+        b_mix = step_algorithmic_bytes(C, E, K, spec["nsub"], 4)
         line["mixed"] = {"value": C * K * args.steps / (ms2 / 1e3), "ms_per_step": ms2 / args.steps,
+                         "step_hbm_effective_frac": round(b_mix / (ms2 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          "speedup_vs_fp64": ms / ms2, "rel_l2_vs_fp64": errs,
                          "after_steps": 2 * args.steps + args.warmup,
                          "mass_rel_diff_vs_fp64": d2["mass"] / diag["mass"] - 1.0,
                          "tiles": {k: f"{t}x{l}" for k, (t, l) in R2["tiles"].items()},
                          "kernels": {n: round(1e3 * t / c, 2) for n, (c, t) in R2["prof"].items() if c}}
-    if not args.no_theta:
+    if args.theta:
         # the optional theta_v/exner diffusion, same timing: what it adds to a step
         print("[bench] theta_v diffusion run", file=sys.stderr, flush=True)
         R3 = run(args.precision, args.steps, args.warmup, tune, params=D.default_params(diffuse_theta=1))
@@ -562,9 +694,24 @@ def main():
                                    "diff_cell_vertex2_us": round(1e3 * R3["prof"]["diff_cell_vertex2"][1]
                                                                  / R3["prof"]["diff_cell_vertex2"][0], 2)}
     G.close()
+    secondary = "r2b5_k65" if args.workload != "r2b5_k65" else None
+    cpu_case = (spec, g0, S0, vert) if secondary is None else None
+    # the headline's host copies are no longer needed (R2B8: ~21 GB each)
+    del S, S0, out, R1
+    if "R2" in locals():
+        del R2, out2
+    if secondary is not None and not args.no_secondary:
+        line["r2b5_k65"] = bench_r2b5(args, D, torch, dev)
     if not args.no_cpu_baseline:
         print("[bench] oracle on the host", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(spec, g0, S, vert)
+        if cpu_case is not None:
+            line["cpu_baseline"] = cpu_baseline(*cpu_case)
+        else:
+            # the oracle on the R2B5 workload: an R2B8 step is beyond the host
+            gb, Sb, vb, sb = build_workload(secondary)
+            line["cpu_baseline"] = cpu_baseline(sb, gb, Sb, vb)
+            line["cpu_baseline"]["sample"] = "R2B5 / 65-level workload (the R2B8 grid is beyond the host): " + \
+                line["cpu_baseline"]["sample"]
     print(json.dumps(line), flush=True)
 
 

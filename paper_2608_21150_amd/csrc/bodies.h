@@ -639,6 +639,10 @@ struct BCol {
       __syncthreads();
       if (p > 0) xa = s_red[4 * sP + (p - 1) * 64 + cl];
       if (p < P - 1) xb = s_red[5 * sP + p * 64 + cl];
+      // every wave has read its interface values before any wave of a
+      // persistent block writes the next tile's system into s_red (P is
+      // uniform over the block, so every wave reaches this barrier)
+      __syncthreads();
     }
     // ---- back substitution and sponge: w* at half levels s..s+n-1 ----
     // (row i of the chunk is half level s + i; w*(h) of the chunk above is

@@ -402,7 +402,13 @@ dc_status dc_ensemble_autotune(dc_ensemble* E, double dt, int32_t nsub, const ch
       }
     }
   }
-  // snapshot the members' current state: the trial steps advance it
+  // snapshot the members' current state: the trial steps advance it.  The
+  // copies run on the null stream, which is not ordered against the
+  // ensemble's non-blocking stream or the members' streams: let the work
+  // queued there finish first
+  if (hipStreamSynchronize(E->stream) != hipSuccess) return efail(DC_EHIP, "ensemble stream synchronisation failed");
+  for (dc_state* s : E->m)
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return efail(DC_EHIP, "member stream synchronisation failed");
   std::vector<std::vector<void*>> saved(E->m.size());
   const int parity = E->m[0]->cur;
   auto release = [&]() {

@@ -201,9 +201,10 @@ def test_mixed_precision_error_vs_fp64():
     b, db = run_gpu(g0, vert, S, spec["dt"], spec["nsub"], 10, precision="mixed")
     errs = {k: rel_l2(b[k], a[k]) for k in FIELDS}
     print("mixed vs fp64 after 10 steps:", errs, "mass rel drift", db["mass"] / da["mass"] - 1)
-    for k in ("vn", "rho", "exner", "theta_v"):
+    for k in FIELDS:
         assert errs[k] <= 1e-4, (k, errs[k])
     assert abs(db["mass"] / da["mass"] - 1) < 1e-12
+    assert abs(db["theta_mass"] / da["theta_mass"] - 1) < 1e-12
 
 
 def test_theta_diffusion_parity_and_batching():
