@@ -260,6 +260,20 @@ dc_status dc_ensemble_create(dc_state *const *members, int32_t n_members, dc_ens
 dc_status dc_ensemble_step(dc_ensemble *ens, double dt, int32_t nsubsteps);
 /* The same step launched eagerly (no graph), synchronising. */
 dc_status dc_ensemble_step_eager(dc_ensemble *ens, double dt, int32_t nsubsteps);
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): dc_ensemble_step_eager without its
+ * per-call allocation.  The step's work tables (one (member, tile) table per
+ * phase) are copied into a static device array of DC_STATIC_PLAN_BYTES
+ * that each GPU the library runs on holds until the process ends, instead
+ * of into memory allocated for the call; nothing is allocated or freed on
+ * the device.  Same kernels, same results as dc_ensemble_step_eager, bit for
+ * bit.  Synchronising.  DC_EINVAL, with nothing enqueued, when the tables
+ * exceed the array (about 9 KB per phase for 24 members; a step has
+ * 6 nsubsteps + 5 phases).  Every call on one GPU shares that GPU's array
+ * and overwrites it: calls that overlap on one GPU (other host threads, or
+ * ensembles on streams not ordered against each other) race. */
+#define DC_STATIC_PLAN_BYTES (2u << 20)
+dc_status dc_ensemble_step_noalloc(dc_ensemble *ens, double dt, int32_t nsubsteps);
 /* Pick the tile/grid schedule of every phase by timing candidates on the
  * ensemble itself (members' states are restored afterwards).  cache_path
  * (may be NULL): a text file of "key<TAB>schedule" lines; a matching key is

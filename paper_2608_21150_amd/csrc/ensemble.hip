@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -216,9 +217,58 @@ dc_status upload_plan(const std::vector<char>& blob, void** dev) {
   return DC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free eager step: the step's work tables go into a file-scope
+// device array instead of memory allocated per call.  Each GPU holds its own
+// copy of the array; its address comes from hipGetSymbolAddress once per
+// device (the array's name is a host-side stand-in, never a device address)
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticPlanBytes = (size_t)DC_STATIC_PLAN_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticPlanBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on device dev (looked up on first use, with dev
+// current)
+dc_status scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return efail(DC_EINVAL, "device id out of range for the static work table");
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    EN_TRY(hipGetDevice(&cur));
+    if (cur != dev) EN_TRY(hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return efail(DC_EHIP, std::string("hipGetSymbolAddress(static work table): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DC_OK;
+}
+
+enum class StepMode { Graph, Eager, Static };
+
 template <typename R>
-dc_status step_impl(dc_ensemble* E, double dt, int nsub, bool eager, Prof* prof) {
+dc_status step_impl(dc_ensemble* E, double dt, int nsub, StepMode mode, Prof* prof) {
   const int parity = E->m[0]->cur;
+  // eager modes: plan on the host first, so that a plan too large for the
+  // static table is refused before anything is enqueued
+  std::vector<char> blob;
+  std::vector<Rec> recs;
+  void* table = nullptr;
+  if (mode != StepMode::Graph) plan_step<R>(E, dt, nsub, parity, blob, recs);
+  if (mode == StepMode::Static) {
+    if (blob.size() > kStaticPlanBytes)
+      return efail(DC_EINVAL, "the step's work tables (" + std::to_string(blob.size()) +
+                                  " bytes) exceed the static table of " + std::to_string(kStaticPlanBytes) +
+                                  " bytes: use fewer members or substeps, or dc_ensemble_step_eager");
+    const dc_status st = scratch_address(E->m[0]->grid->device, &table);
+    if (st != DC_OK) return st;
+  }
   // the ensemble stream waits for work already queued on the members' streams
   for (size_t i = 0; i < E->m.size(); ++i) {
     bool seen = false;
@@ -227,17 +277,18 @@ dc_status step_impl(dc_ensemble* E, double dt, int nsub, bool eager, Prof* prof)
     EN_TRY(hipEventRecord(E->ready, E->m[i]->stream));
     EN_TRY(hipStreamWaitEvent(E->stream, E->ready, 0));
   }
-  if (eager) {
-    std::vector<char> blob;
-    std::vector<Rec> recs;
-    plan_step<R>(E, dt, nsub, parity, blob, recs);
-    void* dev = nullptr;
-    dc_status st = upload_plan(blob, &dev);
-    if (st != DC_OK) return st;
-    launch_recs<R>(E, recs, static_cast<const char*>(dev), E->stream, prof);
+  if (mode != StepMode::Graph) {
+    if (mode == StepMode::Eager) {
+      const dc_status st = upload_plan(blob, &table);
+      if (st != DC_OK) return st;
+    } else {
+      // the host blob outlives the copy: the stream is synchronised below
+      EN_TRY(hipMemcpyAsync(table, blob.data(), blob.size(), hipMemcpyHostToDevice, E->stream));
+    }
+    launch_recs<R>(E, recs, static_cast<const char*>(table), E->stream, prof);
     hipError_t e = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(E->stream);
-    (void)hipFree(dev);
+    if (mode == StepMode::Eager) (void)hipFree(table);
     if (e != hipSuccess || e2 != hipSuccess)
       return efail(DC_EHIP, std::string("batched step: ") + hipGetErrorString(e != hipSuccess ? e : e2));
   } else {
@@ -269,9 +320,9 @@ dc_status step_impl(dc_ensemble* E, double dt, int nsub, bool eager, Prof* prof)
   return DC_OK;
 }
 
-dc_status ens_step(dc_ensemble* E, double dt, int nsub, bool eager, Prof* prof) {
-  if (E->prec == DC_PREC_MIXED) return step_impl<float>(E, dt, nsub, eager, prof);
-  return step_impl<double>(E, dt, nsub, eager, prof);
+dc_status ens_step(dc_ensemble* E, double dt, int nsub, StepMode mode, Prof* prof) {
+  if (E->prec == DC_PREC_MIXED) return step_impl<float>(E, dt, nsub, mode, prof);
+  return step_impl<double>(E, dt, nsub, mode, prof);
 }
 
 std::string tune_key(const dc_ensemble* E) {
@@ -375,7 +426,7 @@ dc_status dc_ensemble_step(dc_ensemble* E, double dt, int32_t nsub) {
   if (nsub < 1 || nsub > 1000) return efail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
   for (const dc_state* s : E->m)
     if (s->cur != E->m[0]->cur) return efail(DC_ESTATE, "members were stepped individually (buffer sets differ)");
-  return ens_step(E, dt, nsub, false, nullptr);
+  return ens_step(E, dt, nsub, StepMode::Graph, nullptr);
 }
 
 dc_status dc_ensemble_step_eager(dc_ensemble* E, double dt, int32_t nsub) {
@@ -384,7 +435,16 @@ dc_status dc_ensemble_step_eager(dc_ensemble* E, double dt, int32_t nsub) {
   if (nsub < 1 || nsub > 1000) return efail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
   for (const dc_state* s : E->m)
     if (s->cur != E->m[0]->cur) return efail(DC_ESTATE, "members were stepped individually (buffer sets differ)");
-  return ens_step(E, dt, nsub, true, nullptr);
+  return ens_step(E, dt, nsub, StepMode::Eager, nullptr);
+}
+
+dc_status dc_ensemble_step_noalloc(dc_ensemble* E, double dt, int32_t nsub) {
+  if (!E) return efail(DC_EINVAL, "ensemble is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return efail(DC_EINVAL, "dt must be finite and > 0");
+  if (nsub < 1 || nsub > 1000) return efail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
+  for (const dc_state* s : E->m)
+    if (s->cur != E->m[0]->cur) return efail(DC_ESTATE, "members were stepped individually (buffer sets differ)");
+  return ens_step(E, dt, nsub, StepMode::Static, nullptr);
 }
 
 dc_status dc_ensemble_autotune(dc_ensemble* E, double dt, int32_t nsub, const char* cache_path) {
@@ -459,7 +519,7 @@ dc_status dc_ensemble_autotune(dc_ensemble* E, double dt, int32_t nsub, const ch
   int best_colg[2] = {0, 0};
   dc_status st = DC_OK;
   // warm-up
-  st = ens_step(E, dt, nsub, true, nullptr);
+  st = ens_step(E, dt, nsub, StepMode::Eager, nullptr);
   for (size_t ci = 0; ci < cands.size() && st == DC_OK; ++ci) {
     for (int t = 0; t < T_COUNT; ++t) E->tiles[t] = {cands[ci].threads, cands[ci].kb};
     std::fill(E->gfac, E->gfac + K_COUNT, cands[ci].gfac);
@@ -467,7 +527,7 @@ dc_status dc_ensemble_autotune(dc_ensemble* E, double dt, int32_t nsub, const ch
     for (int rep = 0; rep < 2 && st == DC_OK; ++rep) {
       E->prof.on = true;
       E->prof.used = 0;
-      st = ens_step(E, dt, nsub, true, &E->prof);
+      st = ens_step(E, dt, nsub, StepMode::Eager, &E->prof);
       E->prof.on = false;
       double cur[K_COUNT] = {0};
       for (size_t i = 0; i + 1 < E->prof.used; ++i)

@@ -138,6 +138,7 @@ def _load():
         "dc_ensemble_step": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
         "dc_ensemble_destroy": (ctypes.c_int, [_p]),
         "dc_ensemble_step_eager": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
+        "dc_ensemble_step_noalloc": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
         "dc_ensemble_autotune": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32, ctypes.c_char_p]),
         "dc_ensemble_schedule": (ctypes.c_int, [_p, ctypes.c_char_p, ctypes.c_size_t]),
         "dc_mlp_create": (ctypes.c_int, [ctypes.c_uint64, ctypes.POINTER(_p)]),
@@ -382,6 +383,11 @@ class Ensemble:
     def step(self, dt: float, nsub: int, eager: bool = False):
         fn = lib.dc_ensemble_step_eager if eager else lib.dc_ensemble_step
         check(fn(self.handle, float(dt), int(nsub)))
+
+    def step_noalloc(self, dt: float, nsub: int):
+        """The eager step with its work tables in the library's static device
+        array (no device allocation; synchronising)."""
+        check(lib.dc_ensemble_step_noalloc(self.handle, float(dt), int(nsub)))
 
     def autotune(self, dt: float, nsub: int, cache_path: str | None = None):
         check(lib.dc_ensemble_autotune(self.handle, float(dt), int(nsub),
