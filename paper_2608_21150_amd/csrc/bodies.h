@@ -523,12 +523,15 @@ struct BCol {
               rn = rr[nb[q]];
               tn = tr[nb[q]];
             }
-            const R rho_e = (R)(0.5 * (cur.rho + rn));
-            const R th_e = (R)(0.5 * (cur.th + tn));
-            const R fm = rho_e * vq[q];
-            const R ft = fm * th_e;
-            dm += kd[q] * (double)fm;
-            dth += kd[q] * (double)ft;
+            // edge means and fluxes in FP64 in both forms (mixed: from the
+            // FP32 vn): an FP32 rounding of the fluxes would add to the
+            // divergence errors that drive w and rho
+            const double rho_e = 0.5 * (cur.rho + rn);
+            const double th_e = 0.5 * (cur.th + tn);
+            const double fm = rho_e * (double)vq[q];
+            const double ft = fm * th_e;
+            dm += kd[q] * fm;
+            dth += kd[q] * ft;
           }
           if (CORR) __builtin_amdgcn_wave_barrier();
           // predictor: divergence of vn* for the corrector's damping (each
