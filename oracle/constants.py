@@ -30,5 +30,7 @@ def default_params():
         "diffuse_theta": 0,     # optional 2nd-order Smagorinsky diffusion of theta_v, exner updated
         "theta_enh_nlev": 0,    # with diffuse_theta: lowest levels whose theta_v coefficient is raised
         "theta_enh_thresh": 5.0,  # ... in cells colder than their neighbours' mean by more than this [K]
+        "miura": 0,             # 1: rho and theta_v at edges by second-order upwind (Miura) reconstruction
+        "vt_rbf": 0,            # 1: tangential wind by RBF vector reconstruction instead of Perot
         "rd": RD, "cpd": CPD, "cvd": CVD, "omega": OMEGA,
     }

@@ -28,10 +28,18 @@ from .constants import default_params
 # ----------------------------------------------------------------------------
 # velocity advection (start of every predictor and corrector pass)
 # ----------------------------------------------------------------------------
+def tangential_wind(g, p, vn):
+    """vt at the edges: Perot reconstruction, or (option vt_rbf) the RBF
+    vector reconstruction of ICON's discretisation (Section 4.1)."""
+    if p.get("vt_rbf", 0):
+        return op.recon_vt_rbf(g, vn)
+    return op.recon_vt(g, vn)
+
+
 def velocity_advection(g, p, vn, w):
     """Advective tendencies (T_vn [K][E], T_w [K+1][C]) in vector-invariant form."""
     K = g.n_lev
-    vt = op.recon_vt(g, vn)
+    vt = tangential_wind(g, p, vn)
     vn_ie = op.ih(vn)
     ke_e = 0.5 * (vn * vn + vt * vt)
     ke_c = op.avg_c(g, ke_e)
@@ -162,8 +170,18 @@ def mass_fluxes(g, vn, rho_e, th_e):
 def predictor(g, p, S, dtau):
     t_vn0, t_w0 = velocity_advection(g, p, S["vn"], S["w"])
     cf = column_coefficients(g, p, S, dtau)
-    rho_e = op.avg_e(g, S["rho"])
-    th_e = op.avg_e(g, S["theta_v"])
+    if p.get("miura", 0):
+        # Section 4.1 keeps ICON's discretisation: the edge values of density
+        # and theta_v by second-order upwind (Miura) reconstruction with the
+        # substep's start winds, used for the fluxes of both passes and for
+        # the pressure-gradient term
+        vt = tangential_wind(g, p, S["vn"])
+        wts = op.cell_gradient_weights(g)
+        rho_e = op.miura_edge(g, S["rho"], S["vn"], vt, dtau, wts)
+        th_e = op.miura_edge(g, S["theta_v"], S["vn"], vt, dtau, wts)
+    else:
+        rho_e = op.avg_e(g, S["rho"])
+        th_e = op.avg_e(g, S["theta_v"])
     grad_ex = op.grad(g, cf["ex_pr"])
     vn_s = S["vn"] + dtau * (t_vn0 - p["cpd"] * th_e * grad_ex)
     dm, dth = mass_fluxes(g, vn_s, rho_e, th_e)

@@ -92,3 +92,101 @@ def ih(q):
 
 def fh(w):
     return 0.5 * (w[:-1] + w[1:])
+
+
+# ----------------------------------------------------------------------------
+# optional operators of the fuller ICON discretisation (Section 4.1: the
+# dynamical core keeps ICON's numerics): least-squares cell gradients and
+# the second-order upwind (Miura) edge values of cell scalars, and the
+# tangential wind by radial-basis-function vector reconstruction
+# ----------------------------------------------------------------------------
+def tangent_basis(x):
+    """Two orthonormal vectors spanning the tangent plane at each unit vector
+    x (N, 3): e1 = normalize(a x x) with a = z_hat (x_hat near the poles),
+    e2 = x x e1."""
+    a = np.where(np.abs(x[:, 2:3]) < 0.9, np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]]))
+    e1 = np.cross(a, x)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(x, e1)
+    return e1, e2
+
+
+def cell_gradient_weights(g):
+    """(C, 3, 3) weights W of the least-squares gradient at the cell centres:
+    grad q_c = sum_i W[c, :, i] (q_{c2e2c[c][i]} - q_c), a vector in the
+    tangent plane at x_c (per metre).  It minimises
+    sum_i (grad . d_i - (q_i - q_c))^2 with d_i the neighbour's offset
+    R (x_i - x_c) projected on that plane, so it reproduces every field that
+    is linear in the plane's coordinates exactly."""
+    e1, e2 = tangent_basis(g.xc)
+    E = np.stack([e1, e2], axis=2)                      # (C, 3, 2)
+    d = g.radius * (g.xc[g.c2e2c] - g.xc[:, None, :])   # (C, 3 nbrs, 3)
+    D = np.einsum("cij,cjk->cik", d, E)                 # (C, 3 nbrs, 2): plane coordinates
+    return np.einsum("cjk,cki->cji", E, np.linalg.pinv(D))  # (C, 3, 3 nbrs)
+
+
+def cell_gradient(g, q, wts=None):
+    """Least-squares gradient (K, C, 3) of a cell field q (K, C)."""
+    if wts is None:
+        wts = cell_gradient_weights(g)
+    dq = q[:, g.c2e2c] - q[:, :, None]                  # (K, C, 3 nbrs)
+    return np.einsum("cji,kci->kcj", wts, dq)
+
+
+def miura_edge(g, q, vn, vt, dtau, wts=None):
+    """Second-order upwind edge value of the cell scalar q (K, C) for the
+    normal and tangential winds vn, vt (K, E) over dtau: the value at the
+    departure point x* = R x_e - dtau (vn n_e + vt t_e) of the edge
+    midpoint, extrapolated linearly with the least-squares gradient of the
+    upwind cell (c0 when vn >= 0, the normal pointing c0 -> c1, else c1):
+        q_e = q_up + grad q_up . (x* - R x_up)."""
+    K = q.shape[0]
+    grad = cell_gradient(g, q, wts)
+    up = np.where(vn >= 0.0, g.e2c[:, 0][None, :], g.e2c[:, 1][None, :])  # (K, E)
+    k = np.arange(K)[:, None]
+    xstar = g.radius * g.xe[None] - dtau * (vn[..., None] * g.nrm[None] + vt[..., None] * g.tan[None])
+    off = xstar - g.radius * g.xc[up]
+    return q[k, up] + np.einsum("kej,kej->ke", grad[k, up], off)
+
+
+def rbf_vt_weights(g, scale=0.5):
+    """(E, 5) weights of the tangential wind by vector radial-basis-function
+    interpolation over the edge and its four e2c2e neighbours (stencil order
+    [e, e2c2e[e][0..3]]): the field v(x) = sum_j a_j phi(|x - x_j|) n_j + c,
+    c a constant vector in the tangent plane at x_e, takes the normal winds
+    at the stencil's midpoints (v(x_i) . n_i = vn_i) with sum_j a_j (n_j . b) = 0
+    for both tangent directions b; vt_e = v(x_e) . t_e.  Kernel: the inverse
+    multiquadric phi(r) = (1 + (r / eps)^2)^(-1/2), eps = scale * l_e;
+    positions in metres.  The constant term makes the reconstruction exact
+    for every flow that is uniform in the tangent plane at the edge."""
+    R = g.radius
+    st = np.concatenate([np.arange(g.ne)[:, None], g.e2c2e], axis=1)  # (E, 5)
+    x = R * g.xe[st]                                                  # (E, 5, 3)
+    n = g.nrm[st]
+    eps = scale * g.l_e
+    def phi(r):
+        return 1.0 / np.sqrt(1.0 + (r / eps[:, None, None]) ** 2)
+    r = np.linalg.norm(x[:, :, None, :] - x[:, None, :, :], axis=3)  # (E, 5, 5)
+    A = phi(r) * np.einsum("eik,ejk->eij", n, n)
+    e1, e2 = tangent_basis(g.xe)
+    B = np.stack([np.einsum("eik,ek->ei", n, e1), np.einsum("eik,ek->ei", n, e2)], axis=2)  # (E, 5, 2)
+    M = np.zeros((g.ne, 7, 7))
+    M[:, :5, :5] = A
+    M[:, :5, 5:] = B
+    M[:, 5:, :5] = np.transpose(B, (0, 2, 1))
+    # right-hand side: the evaluation functional v(x_e) . t_e
+    re = np.linalg.norm(x - R * g.xe[:, None, :], axis=2)              # (E, 5)
+    b = np.zeros((g.ne, 7))
+    b[:, :5] = (1.0 / np.sqrt(1.0 + (re / eps[:, None]) ** 2)) * np.einsum("eik,ek->ei", n, g.tan)
+    b[:, 5] = np.einsum("ek,ek->e", g.tan, e1)
+    b[:, 6] = np.einsum("ek,ek->e", g.tan, e2)
+    # M is symmetric: the weights of vn are the first five entries of M^-1 b
+    return np.linalg.solve(M, b[:, :, None])[:, :5, 0]
+
+
+def recon_vt_rbf(g, F, wts=None):
+    """Tangential wind (K, E) of the normal field F (K, E) by the RBF weights."""
+    if wts is None:
+        wts = rbf_vt_weights(g)
+    st = np.concatenate([np.arange(g.ne)[:, None], g.e2c2e], axis=1)
+    return np.einsum("es,kes->ke", wts, F[:, st])

@@ -473,3 +473,40 @@ def test_w_diffusion_pins():
     e1 = np.sum(g.a_c * out["w"] ** 2)
     assert e1 < e0
     assert np.abs(out["w"] - S4["w"]).max() > 1e-6  # it did act
+
+
+@pytest.mark.parametrize("opts", [{"miura": 1}, {"vt_rbf": 1}, {"miura": 1, "vt_rbf": 1}])
+def test_fuller_numerics_options_keep_invariants(opts, r2b2_case, r2b3):
+    """Miura upwind edge values and the RBF tangential wind (Section 4.1:
+    ICON's discretisation) keep the step's invariants: the resting
+    atmosphere stays bitwise at rest, mass and theta-mass are conserved to
+    round-off over 10 steps of the parity case, a horizontally uniform state
+    gets no horizontal tendencies, and the balanced jet stays steady."""
+    g, S, spec = r2b2_case
+    p = default_params()
+    p.update(opts)
+    _, Sr, _, _ = build_workload("r2b2_k30_rest")
+    S1 = Sr
+    for _ in range(3):
+        S1 = dycore.step(g, S1, spec["dt"], spec["nsub"], p)
+    for k in Sr:
+        assert np.array_equal(S1[k], Sr[k]), k
+    d0 = dycore.diag(g, S)
+    S1 = S
+    for _ in range(10):
+        S1 = dycore.step(g, S1, spec["dt"], spec["nsub"], p)
+    d1 = dycore.diag(g, S1)
+    assert abs(d1["mass"] / d0["mass"] - 1.0) <= 1e-13
+    assert abs(d1["theta_mass"] / d0["theta_mass"] - 1.0) <= 1e-13
+    assert d1["n_nonfinite"] == 0 and d1["max_abs_vn"] < 10.0
+    Su, vert = initial_state(r2b3, 12, 20e3, seed=0)
+    gu = Grid(r2b3, vert)
+    Su["theta_v"] = Su["theta_v"] + np.linspace(0.0, 3.0, 12)[:, None]
+    S2 = dycore.step(gu, Su, 300.0, 3, p)
+    assert np.all(S2["vn"] == 0.0)
+    for k in ("w", "rho", "exner", "theta_v"):
+        assert np.all(S2[k] == S2[k][:, :1]), k
+    Sj, vert = initial_state(r2b3, 20, 30e3, seed=0, jet_u0=35.0)
+    gj = Grid(r2b3, vert)
+    S3 = dycore.step(gj, Sj, 300.0, 5, p)
+    assert np.abs(S3["vn"] - Sj["vn"]).max() < 0.05

@@ -158,3 +158,91 @@ def test_scalar_laplacian_spherical_harmonics():
     for l, e in errs.items():
         assert e[0] > e[1] > e[2], (l, e)
         assert e[2] < 0.03, (l, e)
+
+
+# ----------------------------------------------------------------------------
+# optional operators: least-squares gradient, Miura upwind edge values, RBF vt
+# ----------------------------------------------------------------------------
+def test_cell_gradient_exact_for_plane_linear_data(g2):
+    """The least-squares gradient reproduces data that is linear in the
+    tangent-plane coordinates of the cell exactly: sum_i W_i d_i^T is the
+    tangent projector at x_c (so grad (g . d) = P g), and it is tangent."""
+    W = op.cell_gradient_weights(g2)
+    d = g2.radius * (g2.xc[g2.c2e2c] - g2.xc[:, None, :])
+    P = np.eye(3)[None] - g2.xc[:, :, None] * g2.xc[:, None, :]
+    dp = np.einsum("cij,ckj->cki", P, d)  # offsets projected on the plane
+    M = np.einsum("cji,cik->cjk", W, dp)
+    assert np.max(np.abs(M - P)) < 1e-12
+    assert np.max(np.abs(np.einsum("cji,cj->ci", W, g2.xc))) < 1e-12 * np.max(np.abs(W)) * g2.radius
+    # a uniform field has zero gradient, bitwise
+    q = np.full((2, g2.nc), 3.5)
+    assert np.all(op.cell_gradient(g2, q, W) == 0.0)
+
+
+def test_miura_second_order_and_upwind():
+    """Miura edge values: a uniform field comes out unchanged (bitwise); for
+    q = a . x (linear in space) the value at the departure point
+    x* = R x_e - dtau (vn n + vt t) is reached to second order (the error
+    falls about fourfold per refinement, R2B2 -> R2B5; a first-order or
+    centred value would not); the value depends only on the upwind cell and
+    its neighbours."""
+    om, dtau = 1e-5, 60.0
+    a = np.array([0.2, -0.7, 0.4])
+    errs = []
+    for k in (2, 3, 4, 5):
+        g = _grid(2, k, K=1)
+        u = om * g.radius * np.cross(np.array([0.3, 0.5, 0.8]) / np.linalg.norm([0.3, 0.5, 0.8]), g.xe)
+        vn = np.einsum("ej,ej->e", u, g.nrm)[None]
+        vt = np.einsum("ej,ej->e", u, g.tan)[None]
+        q = 100.0 * (g.xc @ a)[None]
+        qe = op.miura_edge(g, q, vn, vt, dtau)
+        xs = g.radius * g.xe - dtau * (vn[0][:, None] * g.nrm + vt[0][:, None] * g.tan)
+        want = 100.0 * (xs / np.linalg.norm(xs, axis=1, keepdims=True)) @ a
+        errs.append(np.sqrt(np.mean((qe[0] - want) ** 2)))
+        if k == 2:
+            assert np.all(op.miura_edge(g, np.full((1, g.nc), 7.25), vn, vt, dtau) == 7.25)
+            # upwind locality: a spike at one cell reaches only edges whose
+            # upwind cell is that cell or one of its neighbours
+            c = 100
+            spike = np.zeros((1, g.nc))
+            spike[0, c] = 1.0
+            se = op.miura_edge(g, spike, vn, vt, dtau)[0]
+            up = np.where(vn[0] >= 0, g.e2c[:, 0], g.e2c[:, 1])
+            near = (up == c) | np.any(g.c2e2c[up] == c, axis=1)
+            assert np.all(se[~near] == 0.0) and np.any(se[near] != 0.0)
+            # reversing the wind switches the upwind cell
+            se2 = op.miura_edge(g, spike, -vn, -vt, dtau)[0]
+            up2 = np.where(-vn[0] >= 0, g.e2c[:, 0], g.e2c[:, 1])
+            assert np.all(up2 != up)
+            near2 = (up2 == c) | np.any(g.c2e2c[up2] == c, axis=1)
+            assert np.all(se2[~near2] == 0.0)
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 < 0.35 * e0, errs
+    assert errs[-1] < 2e-3, errs
+
+
+def test_rbf_vt_exact_for_uniform_tangent_flow_and_converges():
+    """RBF tangential wind: with the constant term, every flow uniform in the
+    tangent plane at the edge is reproduced exactly (the weights map the
+    stencil normals onto t_e in that plane); for solid-body rotation on the
+    sphere the error falls with refinement R2B2 -> R2B5, below Perot's."""
+    errs, errs_p = [], []
+    for k in (2, 3, 4, 5):
+        g = _grid(2, k, K=1)
+        w = op.rbf_vt_weights(g)
+        if k == 2:
+            st = np.concatenate([np.arange(g.ne)[:, None], g.e2c2e], axis=1)
+            s = np.einsum("es,esj->ej", w, g.nrm[st])
+            P = np.eye(3)[None] - g.xe[:, :, None] * g.xe[:, None, :]
+            assert np.max(np.abs(np.einsum("eij,ej->ei", P, s) - g.tan)) < 1e-10
+        om = 1e-5
+        ax = np.array([0.3, 0.5, 0.8]) / np.linalg.norm([0.3, 0.5, 0.8])
+        u = om * g.radius * np.cross(ax, g.xe)
+        vn = np.einsum("ej,ej->e", u, g.nrm)[None]
+        want = np.einsum("ej,ej->e", u, g.tan)
+        errs.append(np.max(np.abs(op.recon_vt_rbf(g, vn, w)[0] - want)) / (om * g.radius))
+        errs_p.append(np.max(np.abs(op.recon_vt(g, vn)[0] - want)) / (om * g.radius))
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 < 0.6 * e0, errs
+    assert all(a < b for a, b in zip(errs, errs_p)), (errs, errs_p)
+    assert errs[-1] < 1e-3
