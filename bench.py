@@ -62,6 +62,8 @@ def kernel_bytes(C, E, V, K, r):
         "diff_edge1": r * KC + r * 4 * KV + r * 2 * KE,
         "diff_cell_vertex2": r * 2 * KE + 8 * 2 * K1C + r * (KC + KV),
         "diff_edge2": r * 3 * KE + r * KC + r * KV + r * KE,
+        # option: reads vn, vt, rho and theta_v of the upwind cell and its neighbours; writes rho_e, theta_e (FP64)
+        "edge_upwind": 2 * r * KE + 8 * 2 * KC + 8 * 2 * KE,
     }
 
 

@@ -142,6 +142,19 @@ typedef struct {
                                the paper's larger coefficients for strong near-surface
                                temperature contrasts (Section 4.1)                        */
   double theta_enh_thresh;  /* that threshold [K] (> 0; 5)                                     */
+  /* Fuller ICON numerics (Section 4.1: the dynamical core keeps ICON's
+   * discretisation); both off by default. */
+  int32_t miura;   /* 1: rho and theta_v at the edges (mass and theta fluxes of both passes,
+                      theta_v of the pressure-gradient term) by second-order upwind (Miura)
+                      reconstruction: the value at the departure point of the edge midpoint
+                      over the substep, x* = x_e - dtau (vn n + vt t), extrapolated linearly
+                      from the upwind cell (c0 when vn >= 0) with its least-squares gradient
+                      over the three neighbour cells; 0: means of the two cells.  Needs the
+                      larger workspace of dc_state_workspace_bytes_params.               */
+  int32_t vt_rbf;  /* 1: tangential wind by vector radial-basis-function reconstruction over
+                      the edge and its four e2c2e neighbours (inverse multiquadric of scale
+                      0.5 l_e, plus a constant vector tangent at the edge, so uniform tangent
+                      flow is exact); 0: Perot's cell-based reconstruction.               */
 } dc_params;
 
 /* Device pointers of the five prognostic fields, [level][entity] padded.
@@ -181,8 +194,12 @@ dc_status dc_params_default(dc_params *p);
 
 /* Bytes of one device field buffer (padded) in the given precision. */
 dc_status dc_field_bytes(const dc_grid *grid, dc_precision prec, int32_t field, size_t *bytes);
-/* Bytes of the caller-provided device workspace a state needs. */
+/* Bytes of the caller-provided device workspace a state needs with the
+ * default parameters; dc_state_workspace_bytes_params for given parameters
+ * (the Miura option adds two edge fields in FP64). */
 dc_status dc_state_workspace_bytes(const dc_grid *grid, dc_precision prec, dc_diffusion diff, size_t *bytes);
+dc_status dc_state_workspace_bytes_params(const dc_grid *grid, const dc_params *params, dc_precision prec,
+                                          dc_diffusion diff, size_t *bytes);
 
 /* Create a state over caller-owned device buffers (borrowed, never freed
  * by the library; keep them alive until dc_state_destroy).  bufA holds the
@@ -214,7 +231,7 @@ dc_status dc_state_destroy(dc_state *st);
  * every launch of dc_dycore_step (paper, Section 4.3.3: the profile of one
  * substep, launch versus execution).  enable != 0 clears and starts the
  * record, 0 stops it.  dc_state_profile_read synchronises and fills one
- * entry per kernel kind (cap >= 11), in kernel-id order: name, launches,
+ * entry per kernel kind (cap >= 12), in kernel-id order: name, launches,
  * summed duration.  dc_state_profile_select limits later records to the
  * kernels whose bit (1u << kernel id) is set in kernel_mask (0 or all ones:
  * every kernel), so that one kernel can be timed inside a run with little

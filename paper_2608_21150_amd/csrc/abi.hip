@@ -47,11 +47,12 @@ size_t elem_size(dc_precision prec) { return prec == DC_PREC_MIXED ? sizeof(floa
 
 struct Layout {
   size_t vt, tvn0, vns, kc, d2, zeta, vv, gw, dvn, wstar, wtmp, ttmp, tw0, fe, tau, dpart, dout;
+  size_t rhoe, the;  // Miura option only
   size_t s_tmlp, s_cl, s_fj, s_fr, s_cnt;  // surrogate mode only
   size_t total;
 };
 
-Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff) {
+Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff, bool miura) {
   const size_t r = elem_size(prec);
   const size_t K = h.K, K1 = h.K + 1;
   size_t off = 0;
@@ -79,6 +80,11 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff)
   const int nblk = (h.nc + 255) / 256 + (h.ne + 255) / 256;
   L.dpart = take(5 * (size_t)nblk * 8);
   L.dout = take(8 * 8);
+  L.rhoe = L.the = 0;
+  if (miura) {
+    L.rhoe = take(K * h.es * 8);
+    L.the = take(K * h.es * 8);
+  }
   L.s_tmlp = L.s_cl = L.s_fj = L.s_fr = L.s_cnt = 0;
   if (diff == DC_DIFF_SURROGATE) {
     L.s_tmlp = take(K * h.es * r);
@@ -140,8 +146,35 @@ dc_status ensure_uploaded(dc_grid* g) {
 #undef UP
   d.fe = nullptr;
   d.tau = nullptr;
+  d.kmiura = nullptr;
   DC_TRY(hipGetDevice(&g->device));
   g->uploaded = true;
+  return DC_OK;
+}
+
+// tables of the optional schemes a state asks for, built and uploaded once
+dc_status ensure_options(dc_grid* g, const dc_params& p) {
+  dc_status st;
+  if (p.vt_rbf && !g->kvt_rbf) {
+    bool ok = false;
+    try {
+      ok = build_rbf_vt(&g->h);
+    } catch (const std::bad_alloc&) {
+      return fail(DC_ENOMEM, "host allocation failed");
+    }
+    if (!ok) return fail(DC_EGRID, "singular RBF system at an edge");
+    if ((st = upload(g, g->h.k_vt_rbf, &g->kvt_rbf)) != DC_OK) return st;
+    std::vector<double>().swap(g->h.k_vt_rbf);
+  }
+  if (p.miura && !g->kmiura) {
+    try {
+      build_miura(&g->h);
+    } catch (const std::bad_alloc&) {
+      return fail(DC_ENOMEM, "host allocation failed");
+    }
+    if ((st = upload(g, g->h.k_miura, &g->kmiura)) != DC_OK) return st;
+    std::vector<double>().swap(g->h.k_miura);
+  }
   return DC_OK;
 }
 
@@ -264,6 +297,8 @@ dc_status dc_params_default(dc_params* p) {
   p->diffuse_theta = 0;
   p->theta_enh_nlev = 0;
   p->theta_enh_thresh = 5.0;
+  p->miura = 0;
+  p->vt_rbf = 0;
   return DC_OK;
 }
 
@@ -347,7 +382,17 @@ dc_status dc_state_workspace_bytes(const dc_grid* g, dc_precision prec, dc_diffu
   if (prec != DC_PREC_FP64 && prec != DC_PREC_MIXED) return fail(DC_EINVAL, "bad precision");
   if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE && diff != DC_DIFF_SURROGATE)
     return fail(DC_EINVAL, "bad diffusion mode");
-  *bytes = workspace_layout(g->h, prec, diff).total;
+  *bytes = workspace_layout(g->h, prec, diff, false).total;
+  return DC_OK;
+}
+
+dc_status dc_state_workspace_bytes_params(const dc_grid* g, const dc_params* params, dc_precision prec,
+                                          dc_diffusion diff, size_t* bytes) {
+  if (!g || !params || !bytes) return fail(DC_EINVAL, "NULL argument");
+  if (prec != DC_PREC_FP64 && prec != DC_PREC_MIXED) return fail(DC_EINVAL, "bad precision");
+  if (diff != DC_DIFF_PLAIN && diff != DC_DIFF_NONE && diff != DC_DIFF_SURROGATE)
+    return fail(DC_EINVAL, "bad diffusion mode");
+  *bytes = workspace_layout(g->h, prec, diff, params->miura != 0).total;
   return DC_OK;
 }
 
@@ -363,7 +408,9 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   for (int i = 0; i < 2; ++i)
     for (int f = 0; f < DC_FIELD_COUNT; ++f)
       if (!aligned(field_ptr(*bs[i], f))) return fail(DC_EINVAL, "field buffers must be non-NULL and 256-byte aligned");
-  const Layout L = workspace_layout(g->h, prec, diff);
+  if ((params->miura != 0 && params->miura != 1) || (params->vt_rbf != 0 && params->vt_rbf != 1))
+    return fail(DC_EINVAL, "miura and vt_rbf must be 0 or 1");
+  const Layout L = workspace_layout(g->h, prec, diff, params->miura != 0);
   if (!aligned(workspace)) return fail(DC_EINVAL, "workspace must be non-NULL and 256-byte aligned");
   if (ws_bytes < L.total) return fail(DC_EINVAL, "workspace too small: need " + std::to_string(L.total) + " bytes");
   const dc_params& p = *params;
@@ -380,6 +427,7 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
     return fail(DC_EINVAL, "theta_v diffusion is available with the plain diffusion only");
   dc_status st = ensure_uploaded(g);
   if (st != DC_OK) return st;
+  if ((st = ensure_options(g, p)) != DC_OK) return st;
   int dev = -1;
   DC_TRY(hipGetDevice(&dev));
   if (dev != g->device) return fail(DC_EINVAL, "state must be created on the grid's device");
@@ -413,6 +461,10 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->tau = reinterpret_cast<double*>(w + L.tau);
   s->diag_part = reinterpret_cast<double*>(w + L.dpart);
   s->diag_out = reinterpret_cast<double*>(w + L.dout);
+  if (p.miura) {
+    s->rhoe = reinterpret_cast<double*>(w + L.rhoe);
+    s->the = reinterpret_cast<double*>(w + L.the);
+  }
   if (diff == DC_DIFF_SURROGATE) {
     s->sur_tmlp = w + L.s_tmlp;
     s->sur_cl = w + L.s_cl;
@@ -446,6 +498,8 @@ dc_status dc_state_create(const dc_grid* gc, const dc_params* params, dc_precisi
   s->d = g->d;
   s->d.fe = s->fe;
   s->d.tau = s->tau;
+  if (p.vt_rbf) s->d.kvt = g->kvt_rbf;
+  s->d.kmiura = p.miura ? g->kmiura : nullptr;
   default_tiles(h, s->tiles);
   g->states.fetch_add(1);
   *out = s;
@@ -594,7 +648,7 @@ dc_status dc_state_autotune(dc_state* s, double dt, int32_t nsub) {
     }
   }
   static const std::vector<std::vector<int>> uses = {
-      {K_VC_P, K_VC_C}, {K_EDGE_P, K_EDGE_C}, {K_DVERT}, {K_DDIV, K_DCV2}, {K_DEDGE1, K_DEDGE2}};
+      {K_VC_P, K_VC_C}, {K_EDGE_P, K_EDGE_C, K_MIURA}, {K_DVERT}, {K_DDIV, K_DCV2}, {K_DEDGE1, K_DEDGE2}};
   const Tile tile0[T_COUNT] = {s->tiles[0], s->tiles[1], s->tiles[2], s->tiles[3], s->tiles[4]};
   const bool prof_on = s->prof.on;
   const unsigned prof_mask = s->prof.mask;

@@ -179,6 +179,76 @@ struct BVc {
 };
 
 // ---------------------------------------------------------------------------
+// edge (option): rho and theta_v at the edges by second-order upwind (Miura)
+// reconstruction from the state at the start of the substep and its winds
+// vn, vt: q_e = q_up + sum_i w_i (q_i - q_up) over the upwind cell's three
+// neighbours, w_i = a_i - dtau (vn b_i + vt c_i) from the host's per-edge,
+// per-side coefficients (the least-squares gradient dotted with the offset
+// from the upwind cell centre to the departure point of the edge midpoint).
+// In FP64 in both forms; stored for the edge and column kernels of both
+// passes.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct BMiura {
+  struct Args {
+    const R* vn;
+    const R* vt;
+    const double* rho;
+    const double* th;
+    double* rhoe;
+    double* the;
+    double dtau;
+    int kb;
+  };
+  static constexpr int kThreads = 256;
+  __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
+    const int e = bx * blockDim.x + threadIdx.x;
+    if (e >= g.ne) return;
+    const R* __restrict__ vn = args.vn;
+    const R* __restrict__ vt = args.vt;
+    const double* __restrict__ rho = args.rho;
+    const double* __restrict__ th = args.th;
+    double* __restrict__ rhoe = args.rhoe;
+    double* __restrict__ the = args.the;
+    int cu[2], nb[2][3];
+    double ca[2][3], cb[2][3], cc[2][3];
+  #pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      cu[s] = g.e2c[s * g.es + e];
+  #pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        nb[s][i] = g.c2e2c[i * g.cs + cu[s]];
+        ca[s][i] = g.kmiura[(9 * s + i) * g.es + e];
+        cb[s][i] = g.kmiura[(9 * s + 3 + i) * g.es + e];
+        cc[s][i] = g.kmiura[(9 * s + 6 + i) * g.es + e];
+      }
+    }
+    const double dtau = args.dtau;
+    const int kb = args.kb;
+    const int k0 = by * kb, k1 = min(g.K, k0 + kb);
+    for (int k = k0; k < k1; ++k) {
+      const size_t re = (size_t)k * g.es + e;
+      const double v = (double)vn[re], t = (double)vt[re];
+      const bool s0 = v >= 0.0;  // the normal points c0 -> c1: c0 is upwind
+      const int up = s0 ? cu[0] : cu[1];
+      const double* rr = rho + (size_t)k * g.cs;
+      const double* tr = th + (size_t)k * g.cs;
+      const double r0 = rr[up], t0 = tr[up];
+      double ra = r0, ta = t0;
+  #pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int n = s0 ? nb[0][i] : nb[1][i];
+        const double w = (s0 ? ca[0][i] : ca[1][i]) - dtau * (v * (s0 ? cb[0][i] : cb[1][i]) + t * (s0 ? cc[0][i] : cc[1][i]));
+        ra += w * (rr[n] - r0);
+        ta += w * (tr[n] - t0);
+      }
+      rhoe[re] = ra;
+      the[re] = ta;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
 // edge: advective tendency T_vn and the horizontal momentum update.
 //  predictor: vn* = vn + dtau (T_vn - cpd theta_e grad pi')       -> vns, and
 //             Y = vn + dtau (a0 T_vn - cpd theta_e grad pi')        -> tvn0
@@ -200,6 +270,7 @@ struct BEdge {
     R* vout;
     const R* d2;
     R* gw;  // out: l_e vn_ie (w_c1 - w_c0) at the half levels 1..K-1
+    const double* the;  // Miura theta_v at the edges (option; predictor)
     StepCoef cf;
     int kb;
   };
@@ -282,7 +353,7 @@ struct BEdge {
         // corrector needs of the three
         const double exr = exref[j];
         const R gex = (R)((ex[rc + c1] - exr) - (ex[rc + c0] - exr)) * invd_r;
-        const R the = (R)(0.5 * (th[rc + c0] + th[rc + c1]));
+        const R the = cf.miura ? (R)args.the[re] : (R)(0.5 * (th[rc + c0] + th[rc + c1]));
         const R pgf = (R)cf.cpd * the * gex;
         if (in) {
           tvn0[re] = vj + (R)cf.dtau * ((R)cf.a0 * tvn - pgf);
@@ -327,6 +398,7 @@ struct ColArgs {
   R* dv_out;                         // predictor: D = div vn* at the full levels
   const double* ws;                  // corrector: predicted w* (T_w*)
   double *w_out, *rho_out, *ex_out, *th_out;
+  const double *rhoe, *the;          // Miura rho, theta_v at the edges (option)
 };
 
 // T_w at half level k (1 <= k <= K-1) of column c: horizontal part from the
@@ -386,7 +458,7 @@ struct BCol {
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const ColArgs<R>& a = args.a;
     body(g, args.cf, args.P, bx, g.vert, g.tau, a.w, a.rho, a.ex, a.th, a.gw, a.vnf, a.tw0, a.dv_out, a.ws, a.w_out,
-         a.rho_out, a.ex_out, a.th_out);
+         a.rho_out, a.ex_out, a.th_out, a.rhoe, a.the);
   }
   // The fields as restrict parameters: the compiler may then move the loads
   // of later levels above the stores of earlier ones (no buffer is both read
@@ -399,7 +471,8 @@ struct BCol {
                                               R* __restrict__ ptw0, R* __restrict__ pdv,
                                               const double* __restrict__ pws, double* __restrict__ pw_out,
                                               double* __restrict__ prho_out, double* __restrict__ pex_out,
-                                              double* __restrict__ pth_out) {
+                                              double* __restrict__ pth_out, const double* __restrict__ prhoe,
+                                              const double* __restrict__ pthe) {
     // LDS: [6][P][64] interface system; s_stg (corrector): each wave's row
     // of rho and theta_v at its current level (neighbour gathers inside the
     // tile)
@@ -505,33 +578,46 @@ struct BCol {
             __builtin_amdgcn_wave_barrier();
           }
           R vq[3];
+          if (cf.miura) {
+            // Miura edge values stored by the upwind pass
+            const double* er = prhoe + (size_t)j * g.es;
+            const double* et = pthe + (size_t)j * g.es;
   #pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            vq[q] = vr[ie[q]];
-            double rn, tn;
-            if (CORR) {
-              // the LDS read is unconditional (masked index), the memory
-              // read only for neighbours outside the tile (written as
-              // selects: an if-statement form makes the gfx950 backend fail
-              // machine verification)
-              const int lq = nb[q] - bx * 64;
-              rn = s_stg[p][0][lq & 63];
-              tn = s_stg[p][1][lq & 63];
-              rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
-              tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
-            } else {
-              rn = rr[nb[q]];
-              tn = tr[nb[q]];
+            for (int q = 0; q < 3; ++q) {
+              vq[q] = vr[ie[q]];
+              const double fm = er[ie[q]] * (double)vq[q];
+              dm += kd[q] * fm;
+              dth += kd[q] * (fm * et[ie[q]]);
             }
-            // edge means and fluxes in FP64 in both forms (mixed: from the
-            // FP32 vn): an FP32 rounding of the fluxes would add to the
-            // divergence errors that drive w and rho
-            const double rho_e = 0.5 * (cur.rho + rn);
-            const double th_e = 0.5 * (cur.th + tn);
-            const double fm = rho_e * (double)vq[q];
-            const double ft = fm * th_e;
-            dm += kd[q] * fm;
-            dth += kd[q] * ft;
+          } else {
+    #pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              vq[q] = vr[ie[q]];
+              double rn, tn;
+              if (CORR) {
+                // the LDS read is unconditional (masked index), the memory
+                // read only for neighbours outside the tile (written as
+                // selects: an if-statement form makes the gfx950 backend fail
+                // machine verification)
+                const int lq = nb[q] - bx * 64;
+                rn = s_stg[p][0][lq & 63];
+                tn = s_stg[p][1][lq & 63];
+                rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
+                tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
+              } else {
+                rn = rr[nb[q]];
+                tn = tr[nb[q]];
+              }
+              // edge means and fluxes in FP64 in both forms (mixed: from the
+              // FP32 vn): an FP32 rounding of the fluxes would add to the
+              // divergence errors that drive w and rho
+              const double rho_e = 0.5 * (cur.rho + rn);
+              const double th_e = 0.5 * (cur.th + tn);
+              const double fm = rho_e * (double)vq[q];
+              const double ft = fm * th_e;
+              dm += kd[q] * fm;
+              dth += kd[q] * ft;
+            }
           }
           if (CORR) __builtin_amdgcn_wave_barrier();
           // predictor: divergence of vn* for the corrector's damping (each
@@ -1217,7 +1303,8 @@ inline Geom geom_of(int phase, const DevGrid& g, const Tile* T) {
       return {nbx, cdiv(g.K, t.kb), t.threads, 0};
     }
     case K_EDGE_P:
-    case K_EDGE_C: {
+    case K_EDGE_C:
+    case K_MIURA: {
       const Tile& t = T[T_EDGE];
       return {cdiv(g.ne, t.threads), cdiv(g.K, t.kb), t.threads, 0};
     }
@@ -1248,6 +1335,7 @@ inline Geom geom_of(int phase, const DevGrid& g, const Tile* T) {
 template <typename R>
 struct SubstepArgs {
   typename BVc<R, false>::Args vc_p;
+  typename BMiura<R>::Args mi;
   typename BEdge<R, false>::Args e_p;
   ColPhaseArgs<R> c_p;
   typename BVc<R, true>::Args vc_c;
@@ -1262,11 +1350,15 @@ SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& 
   const int Pp = col_chunks_lm(g.K, false, &lm), Pc = col_chunks_lm(g.K, true, &lm);
   const int neb = cdiv(g.ne, T[T_VC].threads), nvb = cdiv(g.nv, T[T_VC].threads);
   s.vc_p = {b.vn, b.zeta, b.vt, b.kc, nullptr, nullptr, neb, nvb, T[T_VC].kb};
-  s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, b.gw, c, T[T_EDGE].kb};
-  s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr}, c, Pp};
+  s.mi = {b.vn, b.vt, b.rho, b.th, b.rhoe, b.the, c.dtau, T[T_EDGE].kb};
+  s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, b.gw, b.the, c, T[T_EDGE].kb};
+  s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr, b.rhoe, b.the},
+           c, Pp};
   s.vc_c = {b.vns, b.zeta, b.vt, b.kc, b.d2, b.dvn, neb, nvb, T[T_VC].kb};
-  s.e_c = {b.vns, b.zeta, b.kc, b.vt, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.d2, b.gw, c, T[T_EDGE].kb};
-  s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out}, c, Pc};
+  s.e_c = {b.vns, b.zeta, b.kc, b.vt, b.ws, b.ex, b.th, b.tvn0, b.vn_out, b.d2, b.gw, nullptr, c, T[T_EDGE].kb};
+  s.c_c = {{b.w, b.rho, b.ex, b.th, b.gw, b.vn_out, b.tw0, nullptr, b.ws, b.w_out, b.rho_out, b.ex_out, b.th_out, b.rhoe,
+            b.the},
+           c, Pc};
   return s;
 }
 

@@ -132,6 +132,7 @@ void plan_step(dc_ensemble* E, double dt, int nsub, int parity, std::vector<char
       sa[k] = substep_args<R>(s->d, b, make_coef(s, dt, nsub), E->tiles);
     }
     table(K_VC_P, [&](int k) { return sa[k].vc_p; });
+    if (E->m[0]->p.miura) table(K_MIURA, [&](int k) { return sa[k].mi; });
     table(K_EDGE_P, [&](int k) { return sa[k].e_p; });
     table(K_COL_P, [&](int k) { return sa[k].c_p; });
     table(K_VC_C, [&](int k) { return sa[k].vc_c; });
@@ -194,6 +195,7 @@ void launch_recs(dc_ensemble* E, const std::vector<Rec>& recs, const char* base,
       case K_DDIV: many<BDiv<R>>(r, base, g, s); break;
       case K_DEDGE1: many<BDedge1<R>>(r, base, g, s); break;
       case K_DCV2: many<BDcv2<R>>(r, base, g, s); break;
+      case K_MIURA: many<BMiura<R>>(r, base, g, s); break;
       default: many<BDedge2<R>>(r, base, g, s); break;
     }
     if (prof) prof->mark(s, -1);
@@ -377,6 +379,8 @@ dc_status dc_ensemble_create(dc_state* const* members, int32_t n, dc_ensemble** 
     if (members[i]->diff != members[0]->diff || members[i]->diff == DC_DIFF_SURROGATE)
       return efail(DC_EINVAL, "members must share a plain or disabled diffusion mode");
     if (members[i]->cur != members[0]->cur) return efail(DC_EINVAL, "members must start in the same buffer set");
+    if (members[i]->p.miura != members[0]->p.miura)
+      return efail(DC_EINVAL, "members must share the Miura upwind option");
     if (members[i]->grid->device != members[0]->grid->device) return efail(DC_EINVAL, "members on different devices");
     for (int j = 0; j < i; ++j)
       if (members[j] == members[i]) return efail(DC_EINVAL, "a member appears twice");
@@ -513,7 +517,7 @@ dc_status dc_ensemble_autotune(dc_ensemble* E, double dt, int32_t nsub, const ch
   const Tile tile0[T_COUNT] = {E->tiles[0], E->tiles[1], E->tiles[2], E->tiles[3], E->tiles[4]};
   // per tile kind: phases that use it
   const std::vector<std::vector<int>> uses = {
-      {K_VC_P, K_VC_C}, {K_EDGE_P, K_EDGE_C}, {K_DVERT}, {K_DDIV, K_DCV2}, {K_DEDGE1, K_DEDGE2}};
+      {K_VC_P, K_VC_C}, {K_EDGE_P, K_EDGE_C, K_MIURA}, {K_DVERT}, {K_DDIV, K_DCV2}, {K_DEDGE1, K_DEDGE2}};
   std::vector<double> best_t(T_COUNT, 1e300), best_col(2, 1e300);
   std::vector<Cand> best_c(T_COUNT, cands[0]);
   int best_colg[2] = {0, 0};

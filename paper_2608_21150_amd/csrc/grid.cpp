@@ -158,6 +158,143 @@ void lsq_vertex_weights(const HostGrid& g, int v, double w[3][6]) {
   }
 }
 
+namespace {
+
+// orthonormal pair spanning the tangent plane at the unit vector x
+void plane_basis(V3 x, V3* e1, V3* e2) {
+  const V3 ax = std::fabs(x.y) < 0.9 ? V3{0, 1, 0} : V3{0, 0, 1};
+  V3 a = cross(x, ax);
+  *e1 = scl(a, 1.0 / norm(a));
+  *e2 = cross(x, *e1);
+}
+
+// Solve the n x n system M y = b in place (row-major M, n <= 8) by Gaussian
+// elimination with partial pivoting; false if a pivot vanishes.
+bool solve_small(double* M, double* b, int n) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(M[i * n + k]) > std::fabs(M[piv * n + k])) piv = i;
+    if (!(std::fabs(M[piv * n + k]) > 0.0)) return false;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) std::swap(M[k * n + j], M[piv * n + j]);
+      std::swap(b[k], b[piv]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = M[i * n + k] / M[k * n + k];
+      for (int j = k; j < n; ++j) M[i * n + j] -= f * M[k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double acc = b[k];
+    for (int j = k + 1; j < n; ++j) acc -= M[k * n + j] * b[j];
+    b[k] = acc / M[k * n + k];
+  }
+  return true;
+}
+
+}  // namespace
+
+// Tangential wind by radial-basis-function vector reconstruction (the
+// interpolation of ICON's discretisation, Section 4.1): over the stencil
+// {e, e2c2e[e][0..3]} a field sum_j a_j phi(|x - x_j|) n_j + c, with c a
+// constant vector in the tangent plane at x_e, matches the normal winds at
+// the stencil's midpoints, its coefficients being orthogonal to the
+// constants (sum_j a_j n_j . b = 0 for the plane's two directions b);
+// vt_e = t_e . v(x_e).  phi(r) = 1 / sqrt(1 + (r / eps)^2), eps = 0.5 l_e,
+// positions in metres.  vt_e is linear in the five winds: its weights are
+// the first five entries of the solution of the (symmetric) system with
+// the evaluation functional as right-hand side.  Slot-major [5][es].
+bool build_rbf_vt(HostGrid* g) {
+  const int ne = g->ne, es = g->es;
+  const double R = g->radius;
+  g->k_vt_rbf.assign(5 * (size_t)es, 0.0);
+  for (int e = 0; e < ne; ++e) {
+    int st[5] = {e, g->e2c2e[4 * e], g->e2c2e[4 * e + 1], g->e2c2e[4 * e + 2], g->e2c2e[4 * e + 3]};
+    V3 x[5], n[5];
+    for (int i = 0; i < 5; ++i) {
+      x[i] = scl(ld(g->xe, st[i]), R);
+      n[i] = ld(g->nrm, st[i]);
+    }
+    const double eps = 0.5 * g->l[e];
+    auto phi = [&](double r) { return 1.0 / std::sqrt(1.0 + (r / eps) * (r / eps)); };
+    V3 b1, b2;
+    plane_basis(ld(g->xe, e), &b1, &b2);
+    const V3 t = ld(g->tan, e);
+    double M[49] = {}, rhs[7];
+    for (int i = 0; i < 5; ++i) {
+      for (int j = 0; j < 5; ++j) M[i * 7 + j] = phi(norm(sub(x[i], x[j]))) * dot(n[i], n[j]);
+      M[i * 7 + 5] = M[5 * 7 + i] = dot(n[i], b1);
+      M[i * 7 + 6] = M[6 * 7 + i] = dot(n[i], b2);
+      rhs[i] = phi(norm(sub(x[0], x[i]))) * dot(n[i], t);
+    }
+    rhs[5] = dot(t, b1);
+    rhs[6] = dot(t, b2);
+    if (!solve_small(M, rhs, 7)) return false;
+    // k_vt's slot order: self, then e2c2e[0..3]
+    for (int i = 0; i < 5; ++i) g->k_vt_rbf[i * es + e] = rhs[i];
+  }
+  return true;
+}
+
+// Second-order upwind (Miura) edge values of cell scalars (Section 4.1):
+// q_e = q_up + grad q_up . (x* - R x_up), x* = R x_e - dtau (vn n_e + vt t_e)
+// the departure point of the edge midpoint, up the upwind cell (c0 when
+// vn >= 0), grad the least-squares gradient over the three neighbour cells
+// in the tangent plane at x_up, grad q = sum_i W_i (q_i - q_up).  Per side
+// s (0: c0 upwind, 1: c1) and neighbour i the table holds
+// a_i = W_i . (R x_e - R x_up), b_i = W_i . n_e, c_i = W_i . t_e, so that
+// q_e = q_up + sum_i (a_i - dtau (vn b_i + vt c_i)) (q_i - q_up);
+// slot 9 s + 3 m + i (m: a, b, c), [18][es].
+void build_miura(HostGrid* g) {
+  const int nc = g->nc, ne = g->ne, es = g->es;
+  const double R = g->radius;
+  // gradient weights of every cell: W = [e1 e2] (D^T D)^-1 D^T, D the 3 x 2
+  // plane coordinates of the neighbour offsets
+  std::vector<double> W(9 * (size_t)nc);
+  for (int c = 0; c < nc; ++c) {
+    const V3 xc = ld(g->xc, c);
+    V3 e1, e2;
+    plane_basis(xc, &e1, &e2);
+    double D[3][2];
+    for (int i = 0; i < 3; ++i) {
+      const V3 d = scl(sub(ld(g->xc, g->c2e2c[3 * c + i]), xc), R);
+      D[i][0] = dot(d, e1);
+      D[i][1] = dot(d, e2);
+    }
+    double a = 0, b = 0, cc = 0;
+    for (int i = 0; i < 3; ++i) {
+      a += D[i][0] * D[i][0];
+      b += D[i][0] * D[i][1];
+      cc += D[i][1] * D[i][1];
+    }
+    const double det = a * cc - b * b;
+    for (int i = 0; i < 3; ++i) {
+      const double p0 = (cc * D[i][0] - b * D[i][1]) / det;
+      const double p1 = (a * D[i][1] - b * D[i][0]) / det;
+      const V3 w = add(scl(e1, p0), scl(e2, p1));
+      W[9 * c + 3 * i + 0] = w.x;
+      W[9 * c + 3 * i + 1] = w.y;
+      W[9 * c + 3 * i + 2] = w.z;
+    }
+  }
+  g->k_miura.assign(18 * (size_t)es, 0.0);
+  for (int e = 0; e < ne; ++e) {
+    const V3 xe = scl(ld(g->xe, e), R), n = ld(g->nrm, e), t = ld(g->tan, e);
+    for (int s = 0; s < 2; ++s) {
+      const int c = g->e2c[2 * e + s];
+      const V3 off = sub(xe, scl(ld(g->xc, c), R));
+      for (int i = 0; i < 3; ++i) {
+        const V3 w{W[9 * c + 3 * i], W[9 * c + 3 * i + 1], W[9 * c + 3 * i + 2]};
+        g->k_miura[(9 * s + 0 + i) * es + e] = dot(w, off);
+        g->k_miura[(9 * s + 3 + i) * es + e] = dot(w, n);
+        g->k_miura[(9 * s + 6 + i) * es + e] = dot(w, t);
+      }
+    }
+  }
+}
+
 int build_host_grid(const dc_grid_desc* D, HostGrid* g, std::string* err) {
   auto fail = [&](int code, const std::string& m) {
     *err = m;

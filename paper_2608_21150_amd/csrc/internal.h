@@ -39,6 +39,9 @@ struct HostGrid {
   std::vector<double> k_curl;                     // [6][vs] (0 in pentagon slot 5)
   std::vector<double> k_lsq;                      // [18][vs] row j*6+s: component j, slot s
   std::vector<double> vert;                       // vertical tables, see VertTab
+  // optional schemes, built on first use by a state that asks for them
+  std::vector<double> k_vt_rbf;                   // [5][es] RBF tangential-wind weights
+  std::vector<double> k_miura;                    // [18][es] Miura upwind coefficients
 };
 
 // Offsets (in units of K+1 doubles) of the per-level vertical tables.
@@ -55,6 +58,8 @@ enum VertTab {
 };
 
 int build_host_grid(const dc_grid_desc* desc, HostGrid* g, std::string* err);
+bool build_rbf_vt(HostGrid* g);
+void build_miura(HostGrid* g);
 void lsq_vertex_weights(const HostGrid& g, int v, double w[3][6]);
 
 void set_error(const std::string& msg);

@@ -12,6 +12,7 @@ enum KernelId {
   K_VC_P = 0, K_EDGE_P, K_COL_P,
   K_VC_C, K_EDGE_C, K_COL_C,
   K_DVERT, K_DDIV, K_DEDGE1, K_DCV2, K_DEDGE2,
+  K_MIURA,  // upwind edge values of rho and theta_v (option), once per substep
   K_COUNT
 };
 extern const char* const kKernelNames[K_COUNT];
@@ -65,6 +66,7 @@ struct DevGrid {
   const double* vert;   // [VT_COUNT][K+1]
   const double* fe;     // [es] Coriolis parameter (per state)
   const double* tau;    // [K+1] sponge rate (per state)
+  const double* kmiura; // [18][es] Miura upwind coefficients (per state; null when off)
 };
 
 // Launch geometry of a level-blocked stencil kernel.
@@ -76,6 +78,7 @@ struct Tile {
 struct StepCoef {
   double dtau, dt, eta, a0, a1, cpd, rd_cvd, cvd_rd, c4a2, cs, cap, k4;
   int diffuse_w, diffuse_theta;
+  int miura;             // rho and theta_v at edges by Miura upwind reconstruction
   int theta_enh_nlev;    // lowest levels with the near-surface floor on the theta_v coefficient
   double theta_enh_thr;  // its threshold [K]
 };
@@ -93,6 +96,8 @@ struct Bufs {
   R* gw;        // [K+1][es] edge terms of the horizontal advection of w
   R* dvn;       // [K][cs] div vn* (predictor column kernel -> corrector damping)
   R* tw0;       // [K+1][cs] T_w at the substep start (predictor -> corrector), formed in R
+  double* rhoe;  // [K][es] Miura rho at edges (option; written by the upwind pass, read by the columns)
+  double* the;   // [K][es] Miura theta_v at edges (also the pressure-gradient term's theta_v)
   // outputs of the corrector
   R* vn_out;
   double *w_out, *rho_out, *ex_out, *th_out;

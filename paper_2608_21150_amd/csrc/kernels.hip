@@ -125,7 +125,8 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
 const char* const kKernelNames[K_COUNT] = {
     "vort_ke_pred", "edge_pred", "column_pred",
     "vort_ke_corr", "edge_corr", "column_corr",
-    "diff_vertex", "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2"};
+    "diff_vertex", "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2",
+    "edge_upwind"};
 
 
 int diag_partial_count(const DevGrid& g) {
@@ -163,6 +164,7 @@ void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const
   const SubstepArgs<R> a = substep_args<R>(g, b, c, T);
   // predictor: advective tendencies at the substep start, momentum, column
   one<BVc<R, false>>(K_VC_P, g, a.vc_p, T, s, prof);
+  if (c.miura) one<BMiura<R>>(K_MIURA, g, a.mi, T, s, prof);  // needs vt of the start vn
   one<BEdge<R, false>>(K_EDGE_P, g, a.e_p, T, s, prof);
   one_col<R, false>(K_COL_P, g, a.c_p, T, s, prof);
   // corrector: tendencies at the predicted state, damping, momentum, column

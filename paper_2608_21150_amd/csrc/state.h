@@ -25,6 +25,9 @@ struct dc_grid {
   int device = -1;
   std::vector<void*> allocs;
   std::atomic<int> states{0};
+  // tables of the optional schemes, uploaded on first use
+  const double* kvt_rbf = nullptr;  // [5][es] RBF tangential-wind weights
+  const double* kmiura = nullptr;   // [18][es] Miura upwind coefficients
 };
 
 struct dc_state {
@@ -48,6 +51,7 @@ struct dc_state {
   void *vt, *tvn0, *vns, *kc, *d2, *zeta, *vv, *gw, *dvn;
   double *wstar, *wtmp, *ttmp, *fe, *tau, *diag_part, *diag_out;
   void* tw0;  // [K+1][cs] T_w of the predictor, in the stencil precision
+  double *rhoe = nullptr, *the = nullptr;  // [K][es] Miura edge values (option)
   // surrogate diffusion (DC_DIFF_SURROGATE only): network tendency [K][es],
   // curl L1 of the diffusion front [K][vs], judge and range flags [es],
   // counters (4 int, then one 64-bit)
@@ -81,6 +85,7 @@ inline StepCoef make_coef(const dc_state* s, double dt, int nsub) {
   c.diffuse_theta = s->p.diffuse_theta;
   c.theta_enh_nlev = s->p.theta_enh_nlev;
   c.theta_enh_thr = s->p.theta_enh_thresh;
+  c.miura = s->p.miura;
   return c;
 }
 
@@ -108,6 +113,8 @@ Bufs<R> substep_bufs(const dc_state* s, int cur_idx, bool w_to_staging) {
   b.gw = static_cast<R*>(s->gw);
   b.dvn = static_cast<R*>(s->dvn);
   b.tw0 = static_cast<R*>(s->tw0);
+  b.rhoe = s->rhoe;
+  b.the = s->the;
   b.vn_out = static_cast<R*>(nxt.vn);
   b.w_out = w_to_staging ? s->wtmp : static_cast<double*>(nxt.w);
   b.rho_out = static_cast<double*>(nxt.rho);

@@ -21,7 +21,7 @@ DIFF = {"plain": 0, "surrogate": 1, "none": 2}
 FIELDS = ("vn", "w", "rho", "exner", "theta_v")
 # kernel ids of the per-kernel profile, and the five launch-tile families
 KERNELS = ("vort_ke_pred", "edge_pred", "column_pred", "vort_ke_corr", "edge_corr", "column_corr", "diff_vertex",
-           "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2")
+           "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2", "edge_upwind")
 TILE_FAMILIES = ("vort_ke", "edge", "diff_vertex", "diff_cell", "diff_edge")
 TABLES = ("e2c", "c2e", "e2v", "c2e2c", "c2v", "v2e", "v2c", "e2c2e", "e2c2v", "perm_cell", "perm_edge", "perm_vert")
 
@@ -60,7 +60,8 @@ class Params(ctypes.Structure):
                 ("eta", "adv_w0", "adv_w1", "divdamp_c4", "rayleigh_tau0", "rayleigh_zfrac", "smag_cs",
                  "smag_cap", "hdiff_k4", "rd", "cpd", "cvd", "omega")] + [
         ("diffuse_w", ctypes.c_int32), ("check_finite", ctypes.c_int32), ("diffuse_theta", ctypes.c_int32),
-        ("theta_enh_nlev", ctypes.c_int32), ("theta_enh_thresh", ctypes.c_double)]
+        ("theta_enh_nlev", ctypes.c_int32), ("theta_enh_thresh", ctypes.c_double),
+        ("miura", ctypes.c_int32), ("vt_rbf", ctypes.c_int32)]
 
 
 class Fields(ctypes.Structure):
@@ -120,6 +121,8 @@ def _load():
         "dc_grid_destroy": (ctypes.c_int, [_p]),
         "dc_field_bytes": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
         "dc_state_workspace_bytes": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+        "dc_state_workspace_bytes_params": (ctypes.c_int, [_p, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int,
+                                                           ctypes.POINTER(ctypes.c_size_t)]),
         "dc_state_create": (ctypes.c_int, [_p, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int, Fields, Fields, _p,
                                            ctypes.c_size_t, _p, ctypes.POINTER(_p)]),
         "dc_state_current": (ctypes.c_int, [_p, ctypes.POINTER(ctypes.c_int32)]),
@@ -268,15 +271,16 @@ class State:
                 check(lib.dc_field_bytes(grid.handle, prec, fi, ctypes.byref(nb)))
                 b[name] = torch.zeros(nb.value, dtype=torch.uint8, device=dev)
             self.bufs.append(b)
+        self.params = params if params is not None else default_params()
         nb = ctypes.c_size_t()
-        check(lib.dc_state_workspace_bytes(grid.handle, prec, DIFF[diffusion], ctypes.byref(nb)))
+        check(lib.dc_state_workspace_bytes_params(grid.handle, ctypes.byref(self.params), prec, DIFF[diffusion],
+                                                  ctypes.byref(nb)))
         self.workspace = torch.zeros(nb.value, dtype=torch.uint8, device=dev)
         fa = Fields(*[self.bufs[0][n].data_ptr() for n in FIELDS])
         fb = Fields(*[self.bufs[1][n].data_ptr() for n in FIELDS])
         if stream is None:
             stream = torch.cuda.current_stream(dev)
         self.stream = stream
-        self.params = params if params is not None else default_params()
         h = _p()
         check(lib.dc_state_create(grid.handle, ctypes.byref(self.params), prec, DIFF[diffusion], fa, fb,
                                   self.workspace.data_ptr(), self.workspace.numel(), _p(stream.cuda_stream),

@@ -139,10 +139,10 @@ def test_params_defaults():
     q = default_params()
     for k in ("eta", "adv_w0", "adv_w1", "divdamp_c4", "rayleigh_tau0", "rayleigh_zfrac", "smag_cs", "smag_cap",
               "hdiff_k4", "rd", "cpd", "cvd", "omega", "diffuse_w", "diffuse_theta", "theta_enh_nlev",
-              "theta_enh_thresh"):
+              "theta_enh_thresh", "miura", "vt_rbf"):
         assert getattr(p, k) == q[k], k
     # the last member sits where the C struct has it: the binding's layout matches
-    assert ctypes.sizeof(D.Params) == 13 * 8 + 4 * 4 + 8
+    assert ctypes.sizeof(D.Params) == 13 * 8 + 4 * 4 + 8 + 2 * 4
 
 
 def test_sizes_and_workspace(grids):

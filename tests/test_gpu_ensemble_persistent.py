@@ -55,11 +55,11 @@ def test_persistent_walk_bitwise_equal_solo(precision, gfac, grids, tmp_path):
     # every phase (persistent grids), loaded without timing
     cells = sorted(grids[ensemble_member(m)["k"]][0]["n_cells"] for m in MEMBERS)
     key = f"prec={0 if precision == 'fp64' else 1};K=65;diff=0;cells=" + ",".join(str(c) for c in cells)
-    sched = "256x11 64x33 256x22 256x6 128x13 | " + " ".join([str(gfac)] * 11)
+    sched = "256x11 64x33 256x22 256x6 128x13 | " + " ".join([str(gfac)] * len(D.KERNELS))
     cache = tmp_path / "sched.txt"
     cache.write_text(f"{key}\t{sched}\n")
     E.autotune(dt, nsub, str(cache))
-    assert E.schedule().split("|")[1].split() == [str(gfac)] * 11
+    assert E.schedule().split("|")[1].split() == [str(gfac)] * len(D.KERNELS)
     # the persistent grids are much smaller than the work tables: every block
     # walks several column tiles (64 columns each) and stencil tiles
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count

@@ -312,3 +312,50 @@ def test_near_surface_enhancement_parity():
     st = D.State(G, params=D.default_params(diffuse_theta=1, theta_enh_nlev=K))  # every level: allowed
     st.close()
     G.close()
+
+
+@pytest.mark.parametrize("opts", [{"miura": 1}, {"vt_rbf": 1}, {"miura": 1, "vt_rbf": 1}])
+def test_fuller_numerics_options_parity(opts):
+    """Miura upwind edge values of rho and theta_v and the RBF tangential
+    wind (Section 4.1, ICON's discretisation) against the oracle with the
+    same options: FP64 after the 10 steps of the R2B2 parity case
+    (<= 1e-11), also curve-ordered; the options change the result; mixed
+    stays close to FP64; an ensemble member equals its solo run."""
+    g0, S, vert, spec = build_workload("r2b2_k30")
+    dt, nsub, steps = spec["dt"], spec["nsub"], spec["steps"]
+    og = OGrid(g0, vert)
+    wts = O.vertex_lsq_weights(og)
+    po = default_params()
+    po.update(opts)
+    ref = S
+    for _ in range(steps):
+        ref = O.step(og, ref, dt, nsub, po, wts=wts)
+    pg = D.default_params(**opts)
+    for sfc in (False, True):
+        out, d = run_gpu(g0, vert, S, dt, nsub, steps, sfc=sfc, params=pg)
+        errs = {k: rel_l2(out[k], ref[k]) for k in FIELDS}
+        print(opts, "sfc" if sfc else "", "rel L2 vs oracle:", errs)
+        for k in FIELDS:
+            assert errs[k] <= 1e-11, (opts, sfc, k, errs[k])
+        assert d["n_nonfinite"] == 0
+    plain, _ = run_gpu(g0, vert, S, dt, nsub, steps)
+    assert rel_l2(out["vn"], plain["vn"]) > 1e-8
+    mixed, _ = run_gpu(g0, vert, S, dt, nsub, steps, precision="mixed", params=pg)
+    for k in FIELDS:
+        assert rel_l2(mixed[k], out[k]) <= 1e-4, (opts, k)
+    G = D.Grid(g0, vert)
+    a = D.State(G, params=pg)
+    b = D.State(G, params=pg)
+    a.write(S)
+    b.write(S)
+    E = D.Ensemble([a])
+    for _ in range(3):
+        E.step(dt, nsub)
+        b.step(dt, nsub)
+    ra, rb = a.read(), b.read()
+    for k in FIELDS:
+        assert np.array_equal(ra[k], rb[k]), (opts, k)
+    E.close()
+    a.close()
+    b.close()
+    G.close()
