@@ -95,6 +95,10 @@ typedef struct {
 typedef struct {
   int32_t n_cells, n_edges, n_verts, n_lev;
   int32_t cell_stride, edge_stride, vert_stride; /* padded level strides, entities */
+  int32_t fused_edge_pass; /* 1: every tile of 256 consecutive edges has its stencil
+                              neighbourhood within the fused edge pass's LDS (a local
+                              numbering, e.g. the generator's or the curve's); 0: the
+                              vorticity/kinetic-energy pass runs separately (same results) */
 } dc_grid_info;
 
 /* Table ids for dc_grid_table (internal numbering; int32, row-major). */

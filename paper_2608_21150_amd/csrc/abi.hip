@@ -147,6 +147,18 @@ dc_status ensure_uploaded(dc_grid* g) {
   d.fe = nullptr;
   d.tau = nullptr;
   d.kmiura = nullptr;
+  d.et_ok = h.et_ok;
+  d.et_ntile = h.et_ntile;
+  d.et_n = d.et_x = d.et_vx = nullptr;
+  d.et_nb = d.et_vl = d.et_ev = nullptr;
+  if (h.et_ok) {
+    if ((st = upload(g, h.et_n, &d.et_n)) != DC_OK) return st;
+    if ((st = upload(g, h.et_x, &d.et_x)) != DC_OK) return st;
+    if ((st = upload(g, h.et_vx, &d.et_vx)) != DC_OK) return st;
+    if ((st = upload(g, h.et_nb, &d.et_nb)) != DC_OK) return st;
+    if ((st = upload(g, h.et_vl, &d.et_vl)) != DC_OK) return st;
+    if ((st = upload(g, h.et_ev, &d.et_ev)) != DC_OK) return st;
+  }
   DC_TRY(hipGetDevice(&g->device));
   g->uploaded = true;
   return DC_OK;
@@ -333,6 +345,7 @@ dc_status dc_grid_info_get(const dc_grid* g, dc_grid_info* info) {
   info->cell_stride = g->h.cs;
   info->edge_stride = g->h.es;
   info->vert_stride = g->h.vs;
+  info->fused_edge_pass = g->h.et_ok;
   return DC_OK;
 }
 

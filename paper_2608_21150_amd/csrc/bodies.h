@@ -84,6 +84,7 @@ struct VtStencil {
 // ---------------------------------------------------------------------------
 template <typename R, bool CORR>
 struct BVc {
+  using Real = R;
   struct Args {
     const R* vn;
     R* zeta;
@@ -190,9 +191,9 @@ struct BVc {
 // ---------------------------------------------------------------------------
 template <typename R>
 struct BMiura {
+  using Real = R;
   struct Args {
     const R* vn;
-    const R* vt;
     const double* rho;
     const double* th;
     double* rhoe;
@@ -205,7 +206,6 @@ struct BMiura {
     const int e = bx * blockDim.x + threadIdx.x;
     if (e >= g.ne) return;
     const R* __restrict__ vn = args.vn;
-    const R* __restrict__ vt = args.vt;
     const double* __restrict__ rho = args.rho;
     const double* __restrict__ th = args.th;
     double* __restrict__ rhoe = args.rhoe;
@@ -223,12 +223,14 @@ struct BMiura {
         cc[s][i] = g.kmiura[(9 * s + 6 + i) * g.es + e];
       }
     }
+    VtStencil<R> vts;  // vt of the start vn, formed here
+    vts.load(g, e);
     const double dtau = args.dtau;
     const int kb = args.kb;
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
     for (int k = k0; k < k1; ++k) {
       const size_t re = (size_t)k * g.es + e;
-      const double v = (double)vn[re], t = (double)vt[re];
+      const double v = (double)vn[re], t = (double)vts.apply(vn + (size_t)k * g.es, e);
       const bool s0 = v >= 0.0;  // the normal points c0 -> c1: c0 is upwind
       const int up = s0 ? cu[0] : cu[1];
       const double* rr = rho + (size_t)k * g.cs;
@@ -258,6 +260,7 @@ struct BMiura {
 // ---------------------------------------------------------------------------
 template <typename R, bool CORR>
 struct BEdge {
+  using Real = R;
   struct Args {
     const R* vn;
     const R* zeta;
@@ -276,59 +279,218 @@ struct BEdge {
   };
   static constexpr bool kXcdRanges = false;  // round-robin tile order (see the top of this file)
   static constexpr int kThreads = 256;
+  // LDS of the fused form: per level parity, vn of the staged edges, vt and
+  // K_e of the tile and its rhombus edges, vorticity at the tile's vertices
+  static constexpr int kBuf = EdgeTiles::XM + 2 * EdgeTiles::XV + EdgeTiles::VM;
+  static constexpr size_t kSmem = 2 * kBuf * sizeof(R);
+
+  // per-edge constants of the edge a thread owns
+  struct Own {
+    int e, c0, c1;
+    bool in;
+    R invd_r, fe, le;
+  };
+  __device__ __forceinline__ static Own own(const DevGrid& g, int e, bool in) {
+    Own o;
+    o.e = e;
+    o.in = in;
+    o.c0 = g.e2c[e];
+    o.c1 = g.e2c[g.es + e];
+    o.invd_r = (R)g.invd[e];
+    o.fe = (R)g.fe[e];
+    o.le = (R)(1.0 / g.invl[e]);
+    return o;
+  }
+
+  // The edge's work at full level j from vn at j - 1, j, j + 1, w at c0, c1
+  // on half levels j and j + 1, the vorticity at the edge, the K_e of its
+  // four rhombus edges and its vt.
+  // The fields are restrict parameters: no buffer is both read and written
+  // by one launch, so loads of later levels may move above earlier stores.
+  __device__ __forceinline__ static void level(const DevGrid& g, const StepCoef& cf, const Own& o, int j, R vup,
+                                               R vj, R vdn, double wa0, double wa1, double wb0, double wb1, R ze,
+                                               const R kq[4], R vt, R* __restrict__ gw, R* __restrict__ tvn0,
+                                               R* __restrict__ vout, const double* __restrict__ ex,
+                                               const double* __restrict__ th, const double* __restrict__ the_m,
+                                               const R* __restrict__ d2) {
+    const int K = g.K;
+    const size_t re = (size_t)j * g.es + o.e;
+    const R ie_top = j > 0 ? R(0.5) * (vup + vj) : vj;
+    const R ie_bot = j < K - 1 ? R(0.5) * (vj + vdn) : vj;
+    // the other two edges of c0, then of c1: K_c1 - K_c0 is a third of the
+    // difference of their kinetic energies (the edge's own K_e cancels)
+    const R kgrad = ((kq[2] + kq[3]) - (kq[0] + kq[1])) * (R(1) / R(3)) * o.invd_r;
+    const R wef = (R)(0.5 * (0.5 * (wa0 + wa1) + 0.5 * (wb0 + wb1)));
+    // this edge's share of the horizontal advection of w at half level j:
+    // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
+    if (j > 0 && o.in) gw[re] = o.le * ie_top * (R)(wa1 - wa0);
+    const R tvn = (ze + o.fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)vt_row(g, VT_IDZF)[j];
+    const size_t rc = (size_t)j * g.cs;
+    if (!CORR) {
+      // the pressure-gradient term comes from the substep's start state in
+      // both passes: the predictor forms it once and stores the start vn
+      // advanced by it and by its share of the tendency,
+      // vn + dtau (a0 T_vn0 - cpd theta_e grad pi'), which is all the
+      // corrector needs of the three
+      const double exr = vt_row(g, VT_EXREF)[j];
+      const R gex = (R)((ex[rc + o.c1] - exr) - (ex[rc + o.c0] - exr)) * o.invd_r;
+      const R the = cf.miura ? (R)the_m[re] : (R)(0.5 * (th[rc + o.c0] + th[rc + o.c1]));
+      const R pgf = (R)cf.cpd * the * gex;
+      if (o.in) {
+        tvn0[re] = vj + (R)cf.dtau * ((R)cf.a0 * tvn - pgf);
+        vout[re] = vj + (R)cf.dtau * (tvn - pgf);
+      }
+    } else {
+      const R dd = (d2[rc + o.c1] - d2[rc + o.c0]) * o.invd_r;
+      if (o.in) vout[re] = tvn0[re] + ((R)cf.dtau * (R)cf.a1 * tvn - (R)cf.c4a2 * dd);
+    }
+  }
+
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
+    if (g.et_ok)
+      fused(g, args, bx, by);
+    else
+      gather(g, args, bx, by);
+  }
+
+  // Fused form: the block's tile of 256 edges stages, at every level, vn of
+  // the tile, of its rhombus edges, of their rhombus edges and of the edges
+  // around the tile's vertices in LDS (host tables list them), forms vt and
+  // K_e on the tile and its rhombus edges and the vorticity at the tile's
+  // vertices there, then each thread does its edge's work.  No vt, K_e or
+  // vorticity field goes through memory.  Threads past the last edge of the
+  // grid do the staging and reach every barrier but store nothing.
+  __device__ static void fused(const DevGrid& g, const Args& args, int bx, int by) {
+    using T = EdgeTiles;
+    extern __shared__ double s_dyn[];
+    R* const sb = reinterpret_cast<R*>(s_dyn);
     const R* __restrict__ vn = args.vn;
-    R* __restrict__ gw = args.gw;
+    const double* __restrict__ w = args.w;
+    const int t = bx, tid = threadIdx.x;
+    const size_t tt = (size_t)t;
+    const int n_own = g.et_n[4 * tt], n_vt = g.et_n[4 * tt + 1], n_ext = g.et_n[4 * tt + 2],
+              n_v = g.et_n[4 * tt + 3];
+    // staged positions tid, tid + 256, tid + 512 of this thread
+    int gx[3];
+  #pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int p = tid + r * T::kTileE;
+      gx[r] = p < n_ext ? g.et_x[tt * T::XM + p] : -1;
+    }
+    // vt and K_e at local positions tid and tid + 256 (the vt set is a
+    // prefix of the staged set, so its global ids are gx[0], gx[1])
+    int nbl[2][4];
+    R wv[2][5];
+    bool hv[2];
+  #pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int l = tid + q * T::kTileE;
+      hv[q] = l < n_vt;
+      const int ge = hv[q] ? gx[q] : 0;
+  #pragma unroll
+      for (int s = 0; s < 4; ++s) nbl[q][s] = hv[q] ? (int)g.et_nb[(tt * 4 + s) * T::XV + l] : 0;
+  #pragma unroll
+      for (int s = 0; s < 5; ++s) wv[q][s] = (R)g.kvt[s * g.es + ge];
+    }
+    // vorticity at local vertex tid
+    const bool hz = tid < n_v;
+    int vl[6];
+    R kc[6];
+    {
+      const int gv = hz ? g.et_vx[tt * T::VM + tid] : 0;
+  #pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        vl[s] = hz ? (int)g.et_vl[(tt * 6 + s) * T::VM + tid] : 0;
+        kc[s] = (R)g.kcurl[s * g.vs + gv];
+      }
+    }
+    // the own edge (local position tid; its rhombus positions are nbl[0])
+    const bool in = tid < n_own;
+    const Own o = own(g, in ? t * T::kTileE + tid : 0, in);
+    const int lv0 = in ? (int)g.et_ev[(tt * 2) * T::kTileE + tid] : 0;
+    const int lv1 = in ? (int)g.et_ev[(tt * 2 + 1) * T::kTileE + tid] : 0;
+    const int K = g.K, kb = args.kb;
+    const int k0 = by * kb, k1 = min(K, k0 + kb);
+    R vup = vn[(size_t)max(k0 - 1, 0) * g.es + o.e];
+    double wa0 = w[(size_t)k0 * g.cs + o.c0], wa1 = w[(size_t)k0 * g.cs + o.c1];
+    for (int j = k0; j < k1; ++j) {
+      R* sv = sb + (j & 1) * kBuf;
+      R* svt = sv + T::XM;
+      R* ske = svt + T::XV;
+      R* sz = ske + T::XV;
+      const R* row = vn + (size_t)j * g.es;
+  #pragma unroll
+      for (int r = 0; r < 3; ++r)
+        if (gx[r] >= 0) sv[tid + r * T::kTileE] = row[gx[r]];
+      // loads that do not wait for the staging
+      const size_t re = (size_t)j * g.es + o.e;
+      const R vdn = j < K - 1 ? vn[re + g.es] : vn[re];
+      const double wb0 = w[(size_t)(j + 1) * g.cs + o.c0], wb1 = w[(size_t)(j + 1) * g.cs + o.c1];
+      __syncthreads();
+  #pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (hv[q]) {
+          const int l = tid + q * T::kTileE;
+          const R a = sv[l];
+          R b = wv[q][0] * a;
+  #pragma unroll
+          for (int s = 0; s < 4; ++s) b += wv[q][1 + s] * sv[nbl[q][s]];
+          svt[l] = b;
+          ske[l] = R(0.5) * (a * a + b * b);
+        }
+      if (hz) {
+        R z = kc[0] * sv[vl[0]];
+  #pragma unroll
+        for (int s = 1; s < 6; ++s) z += kc[s] * sv[vl[s]];
+        sz[tid] = z;
+      }
+      __syncthreads();
+      const R vj = sv[tid];
+      const R ze = R(0.5) * (sz[lv0] + sz[lv1]);
+      R kq[4];
+  #pragma unroll
+      for (int q = 0; q < 4; ++q) kq[q] = ske[nbl[0][q]];
+      level(g, args.cf, o, j, vup, vj, vdn, wa0, wa1, wb0, wb1, ze, kq, svt[tid], args.gw, args.tvn0, args.vout, args.ex,
+            args.th, args.the, args.d2);
+      vup = vj;
+      wa0 = wb0;
+      wa1 = wb1;
+    }
+    __syncthreads();  // the next tile of a persistent block reuses the LDS
+  }
+
+  // Gather form, for grids whose tiles do not fit the fused form's LDS: vt,
+  // K_e and the vorticity come from the vorticity pass through memory; the
+  // rhombus edges' K_e from the block's row in LDS where they lie in the
+  // block.  Threads past the last edge compute edge 0 and store nothing:
+  // every thread reaches the per-level barriers.
+  __device__ static void gather(const DevGrid& g, const Args& args, int bx, int by) {
+    const R* __restrict__ vn = args.vn;
     const R* __restrict__ zeta = args.zeta;
     const R* __restrict__ ke = args.ke;
     const R* __restrict__ vtf = args.vt;
     const double* __restrict__ w = args.w;
-    const double* __restrict__ ex = args.ex;
-    const double* __restrict__ th = args.th;
-    R* __restrict__ tvn0 = args.tvn0;
-    R* __restrict__ vout = args.vout;
-    const R* __restrict__ d2 = args.d2;
-    const StepCoef cf = args.cf;
-    const int kb = args.kb;
-    // threads past the last edge compute edge 0 and store nothing: every
-    // thread reaches the per-level barriers of the K_e staging below
     const int base = bx * blockDim.x;
     const bool in = base + (int)threadIdx.x < g.ne;
-    const int e = in ? base + (int)threadIdx.x : 0;
+    const Own o = own(g, in ? base + (int)threadIdx.x : 0, in);
     __shared__ R s_ke[2][kThreads];
-    const int K = g.K;
-    const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
-    const int v0 = g.e2v[e], v1 = g.e2v[g.es + e];
-    const double invd = g.invd[e];
-    const R invd_r = (R)invd;
-    const R fe = (R)g.fe[e];
-    const R le = (R)(1.0 / g.invl[e]);
-    // the other two edges of c0, then of c1: K_c1 - K_c0 is a third of the
-    // difference of their kinetic energies (the edge's own K_e cancels)
+    const int v0 = g.e2v[o.e], v1 = g.e2v[g.es + o.e];
     int rh[4];
   #pragma unroll
-    for (int s = 0; s < 4; ++s) rh[s] = g.e2c2e[s * g.es + e];
-    const R third = R(1) / R(3);
-    const double* idzf = vt_row(g, VT_IDZF);
-    const double* exref = vt_row(g, VT_EXREF);
+    for (int s = 0; s < 4; ++s) rh[s] = g.e2c2e[s * g.es + o.e];
+    const int K = g.K, kb = args.kb;
     const int k0 = by * kb, k1 = min(K, k0 + kb);
-    // values of the level above and of half level j carried from the
-    // previous level: vn(j-1), vn(j) and w at c0, c1 on half level j
-    R vup = vn[(size_t)max(k0 - 1, 0) * g.es + e];
-    R vj = vn[(size_t)k0 * g.es + e];
-    double wa0 = w[(size_t)k0 * g.cs + c0], wa1 = w[(size_t)k0 * g.cs + c1];
+    R vup = vn[(size_t)max(k0 - 1, 0) * g.es + o.e];
+    R vj = vn[(size_t)k0 * g.es + o.e];
+    double wa0 = w[(size_t)k0 * g.cs + o.c0], wa1 = w[(size_t)k0 * g.cs + o.c1];
     for (int j = k0; j < k1; ++j) {
-      const size_t re = (size_t)j * g.es + e;
+      const size_t re = (size_t)j * g.es + o.e;
       const R vdn = j < K - 1 ? vn[re + g.es] : vj;
-      const double wb0 = w[(size_t)(j + 1) * g.cs + c0], wb1 = w[(size_t)(j + 1) * g.cs + c1];
-      const R ie_top = j > 0 ? R(0.5) * (vup + vj) : vj;
-      const R ie_bot = j < K - 1 ? R(0.5) * (vj + vdn) : vj;
+      const double wb0 = w[(size_t)(j + 1) * g.cs + o.c0], wb1 = w[(size_t)(j + 1) * g.cs + o.c1];
       const R* zr = zeta + (size_t)j * g.vs;
       const R ze = R(0.5) * (zr[v0] + zr[v1]);
-      // K_e of the rhombus edges: from the block's row in LDS where they lie
-      // in the block, else from memory
       const R* kr = ke + (size_t)j * g.es;
-      s_ke[j & 1][threadIdx.x] = kr[e];
+      s_ke[j & 1][threadIdx.x] = kr[o.e];
       __syncthreads();
       R kq[4];
   #pragma unroll
@@ -337,32 +499,8 @@ struct BEdge {
         const R x = s_ke[j & 1][l & (kThreads - 1)];
         kq[q] = (unsigned)l < (unsigned)blockDim.x ? x : kr[rh[q]];
       }
-      const R kgrad = ((kq[2] + kq[3]) - (kq[0] + kq[1])) * third * invd_r;
-      const R wef = (R)(0.5 * (0.5 * (wa0 + wa1) + 0.5 * (wb0 + wb1)));
-      // this edge's share of the horizontal advection of w at half level j:
-      // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
-      if (j > 0 && in) gw[re] = le * ie_top * (R)(wa1 - wa0);
-      const R vt = vtf[re];
-      const R tvn = (ze + fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)idzf[j];
-      const size_t rc = (size_t)j * g.cs;
-      if (!CORR) {
-        // the pressure-gradient term comes from the substep's start state in
-        // both passes: the predictor forms it once and stores the start vn
-        // advanced by it and by its share of the tendency,
-        // vn + dtau (a0 T_vn0 - cpd theta_e grad pi'), which is all the
-        // corrector needs of the three
-        const double exr = exref[j];
-        const R gex = (R)((ex[rc + c1] - exr) - (ex[rc + c0] - exr)) * invd_r;
-        const R the = cf.miura ? (R)args.the[re] : (R)(0.5 * (th[rc + c0] + th[rc + c1]));
-        const R pgf = (R)cf.cpd * the * gex;
-        if (in) {
-          tvn0[re] = vj + (R)cf.dtau * ((R)cf.a0 * tvn - pgf);
-          vout[re] = vj + (R)cf.dtau * (tvn - pgf);
-        }
-      } else {
-        const R dd = (d2[rc + c1] - d2[rc + c0]) * invd_r;
-        if (in) vout[re] = tvn0[re] + ((R)cf.dtau * (R)cf.a1 * tvn - (R)cf.c4a2 * dd);
-      }
+      level(g, args.cf, o, j, vup, vj, vdn, wa0, wa1, wb0, wb1, ze, kq, vtf[re], args.gw, args.tvn0, args.vout,
+            args.ex, args.th, args.the, args.d2);
       vup = vj;
       vj = vdn;
       wa0 = wb0;
@@ -451,6 +589,7 @@ struct ColPhaseArgs {
 
 template <typename R, bool CORR, int LM>
 struct BCol {
+  using Real = R;
   using Args = ColPhaseArgs<R>;
   // the predictor runs up to 12 waves per block, the corrector up to 8 (its
   // registers allow two waves per SIMD only)
@@ -967,6 +1106,7 @@ __device__ __forceinline__ double dif_w(const DevGrid& g, const LapGeo& q, const
 
 template <typename R>
 struct BDvert {
+  using Real = R;
   struct Args {
     const R* vn;
     R* vv;
@@ -1017,6 +1157,7 @@ struct BDvert {
 // cell: divergence of an edge field (first pass: div vn)
 template <typename R>
 struct BDiv {
+  using Real = R;
   struct Args {
     const R* f;
     R* out;
@@ -1048,6 +1189,7 @@ struct BDiv {
 // from the rhombus deformation of the vertex vectors.
 template <typename R>
 struct BDedge1 {
+  using Real = R;
   struct Args {
     const R* dv;
     const R* zeta;
@@ -1086,6 +1228,7 @@ struct BDedge1 {
 // Smagorinsky diffusion of w at cells (reads w_in, writes w_out).
 template <typename R>
 struct BDcv2 {
+  using Real = R;
   struct Args {
     const R* l1;
     const R* nu;
@@ -1186,6 +1329,7 @@ struct BDcv2 {
 // edge: L2 = lapv(L1) and vn += dt nu L1 - k4 A_e^2 L2 (in place).
 template <typename R>
 struct BDedge2 {
+  using Real = R;
   struct Args {
     R* vn;
     const R* l1;
@@ -1293,17 +1437,26 @@ inline int col_chunks_lm(int K, bool corr, int* lm) {
   return std::max(1, (nrow + *lm - 1) / *lm);
 }
 
-inline Geom geom_of(int phase, const DevGrid& g, const Tile* T) {
+// rbytes: bytes of the stencil precision (the fused edge pass's LDS holds it)
+inline Geom geom_of(int phase, const DevGrid& g, const Tile* T, size_t rbytes) {
   int lm;
   switch (phase) {
     case K_VC_P:
     case K_VC_C: {
+      // with the fused edge pass only the corrector's damping field is left
       const Tile& t = T[T_VC];
-      const int nbx = cdiv(g.ne, t.threads) + cdiv(g.nv, t.threads) + (phase == K_VC_C ? cdiv(g.nc, t.threads) : 0);
+      const int nbx = (g.et_ok ? 0 : cdiv(g.ne, t.threads) + cdiv(g.nv, t.threads)) +
+                      (phase == K_VC_C ? cdiv(g.nc, t.threads) : 0);
       return {nbx, cdiv(g.K, t.kb), t.threads, 0};
     }
     case K_EDGE_P:
-    case K_EDGE_C:
+    case K_EDGE_C: {
+      // tiles of EdgeTiles::kTileE edges in both forms (the fused form's
+      // host tables are built for them); only the level blocks are tuned
+      const Tile& t = T[T_EDGE];
+      return {cdiv(g.ne, EdgeTiles::kTileE), cdiv(g.K, t.kb), EdgeTiles::kTileE,
+              g.et_ok ? BEdge<double, false>::kSmem / sizeof(double) * rbytes : 0};
+    }
     case K_MIURA: {
       const Tile& t = T[T_EDGE];
       return {cdiv(g.ne, t.threads), cdiv(g.K, t.kb), t.threads, 0};
@@ -1348,9 +1501,9 @@ SubstepArgs<R> substep_args(const DevGrid& g, const Bufs<R>& b, const StepCoef& 
   SubstepArgs<R> s;
   int lm;
   const int Pp = col_chunks_lm(g.K, false, &lm), Pc = col_chunks_lm(g.K, true, &lm);
-  const int neb = cdiv(g.ne, T[T_VC].threads), nvb = cdiv(g.nv, T[T_VC].threads);
+  const int neb = g.et_ok ? 0 : cdiv(g.ne, T[T_VC].threads), nvb = g.et_ok ? 0 : cdiv(g.nv, T[T_VC].threads);
   s.vc_p = {b.vn, b.zeta, b.vt, b.kc, nullptr, nullptr, neb, nvb, T[T_VC].kb};
-  s.mi = {b.vn, b.vt, b.rho, b.th, b.rhoe, b.the, c.dtau, T[T_EDGE].kb};
+  s.mi = {b.vn, b.rho, b.th, b.rhoe, b.the, c.dtau, T[T_EDGE].kb};
   s.e_p = {b.vn, b.zeta, b.kc, b.vt, b.w, b.ex, b.th, b.tvn0, b.vns, nullptr, b.gw, b.the, c, T[T_EDGE].kb};
   s.c_p = {{b.w, b.rho, b.ex, b.th, b.gw, b.vns, b.tw0, b.dvn, nullptr, b.ws, nullptr, nullptr, nullptr, b.rhoe, b.the},
            c, Pp};

@@ -106,9 +106,11 @@ void plan_step(dc_ensemble* E, double dt, int nsub, int parity, std::vector<char
     std::vector<Job<A>> jobs(nm);
     std::vector<int> ts(nm + 1, 0);
     Geom geo{};
+    size_t smem = 0;  // the largest member's need (fused edge passes use LDS)
     for (int i = 0; i < nm; ++i) {
       const dc_state* s = E->m[i];
-      geo = geom_of(phase, s->d, E->tiles);
+      geo = geom_of(phase, s->d, E->tiles, sizeof(R));
+      smem = std::max(smem, geo.smem);
       jobs[i].g = s->d;
       jobs[i].a = args_of(i);
       jobs[i].nbx = geo.nbx;
@@ -121,7 +123,7 @@ void plan_step(dc_ensemble* E, double dt, int nsub, int parity, std::vector<char
     r.nm = nm;
     r.total = ts[nm];
     r.threads = geo.threads;
-    r.smem = geo.smem;
+    r.smem = smem;
     recs.push_back(r);
   };
   for (int i = 0; i < nsub; ++i) {

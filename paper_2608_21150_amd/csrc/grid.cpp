@@ -295,6 +295,83 @@ void build_miura(HostGrid* g) {
   }
 }
 
+// Tiles of the fused edge pass (layout in internal.h).  Staged order: the
+// tile's own edges in id order, then R1, R2 and the remaining edges around
+// the tile's vertices, each in order of first appearance.
+void build_edge_tiles(HostGrid* g) {
+  using T = EdgeTiles;
+  const int ne = g->ne, nt = (ne + T::kTileE - 1) / T::kTileE;
+  g->et_ok = 0;
+  g->et_ntile = nt;
+  g->et_n.assign(4 * (size_t)nt, 0);
+  g->et_x.assign((size_t)T::XM * nt, 0);
+  g->et_vx.assign((size_t)T::VM * nt, 0);
+  g->et_nb.assign((size_t)4 * T::XV * nt, 0);
+  g->et_vl.assign((size_t)6 * T::VM * nt, 0);
+  g->et_ev.assign((size_t)2 * T::kTileE * nt, 0);
+  std::vector<int> pos(ne, -1), vpos(g->nv, -1);
+  std::vector<int> ext, vert;
+  const int vs = g->vs;
+  for (int t = 0; t < nt; ++t) {
+    const int e0 = t * T::kTileE, e1 = std::min(ne, e0 + T::kTileE);
+    ext.clear();
+    vert.clear();
+    auto add = [&](int e) {
+      if (pos[e] < 0) {
+        pos[e] = (int)ext.size();
+        ext.push_back(e);
+      }
+    };
+    for (int e = e0; e < e1; ++e) add(e);
+    const int n_own = e1 - e0;
+    for (int i = 0; i < n_own; ++i)
+      for (int s = 0; s < 4; ++s) add(g->e2c2e[4 * ext[i] + s]);
+    const int n_vt = (int)ext.size();
+    for (int i = n_own; i < n_vt; ++i)
+      for (int s = 0; s < 4; ++s) add(g->e2c2e[4 * ext[i] + s]);
+    for (int i = 0; i < n_own; ++i)
+      for (int s = 0; s < 2; ++s) {
+        const int v = g->e2v[2 * ext[i] + s];
+        if (vpos[v] < 0) {
+          vpos[v] = (int)vert.size();
+          vert.push_back(v);
+        }
+      }
+    for (int v : vert)
+      for (int s = 0; s < 6; ++s) add(g->t_v2e[s * vs + v]);
+    const int n_ext = (int)ext.size(), n_v = (int)vert.size();
+    const bool fits = n_ext <= T::XM && n_vt <= T::XV && n_v <= T::VM;
+    if (fits) {
+      const size_t tt = t;
+      g->et_n[4 * tt + 0] = n_own;
+      g->et_n[4 * tt + 1] = n_vt;
+      g->et_n[4 * tt + 2] = n_ext;
+      g->et_n[4 * tt + 3] = n_v;
+      for (int p = 0; p < T::XM; ++p) g->et_x[tt * T::XM + p] = ext[p < n_ext ? p : 0];
+      for (int l = 0; l < n_vt; ++l)
+        for (int s = 0; s < 4; ++s) g->et_nb[(tt * 4 + s) * T::XV + l] = (uint16_t)pos[g->e2c2e[4 * ext[l] + s]];
+      for (int v = 0; v < n_v; ++v) {
+        g->et_vx[tt * T::VM + v] = vert[v];
+        for (int s = 0; s < 6; ++s) g->et_vl[(tt * 6 + s) * T::VM + v] = (uint16_t)pos[g->t_v2e[s * vs + vert[v]]];
+      }
+      for (int i = 0; i < n_own; ++i)
+        for (int s = 0; s < 2; ++s) g->et_ev[(tt * 2 + s) * T::kTileE + i] = (uint16_t)vpos[g->e2v[2 * ext[i] + s]];
+    }
+    for (int e : ext) pos[e] = -1;
+    for (int v : vert) vpos[v] = -1;
+    if (!fits) {
+      std::vector<int32_t>().swap(g->et_n);
+      std::vector<int32_t>().swap(g->et_x);
+      std::vector<int32_t>().swap(g->et_vx);
+      std::vector<uint16_t>().swap(g->et_nb);
+      std::vector<uint16_t>().swap(g->et_vl);
+      std::vector<uint16_t>().swap(g->et_ev);
+      return;
+    }
+  }
+  g->et_ok = 1;
+}
+
 int build_host_grid(const dc_grid_desc* D, HostGrid* g, std::string* err) {
   auto fail = [&](int code, const std::string& m) {
     *err = m;
@@ -657,6 +734,7 @@ int build_host_grid(const dc_grid_desc* D, HostGrid* g, std::string* err) {
       for (int j = 0; j < 3; ++j) g->k_lsq[(j * 6 + s) * vs + v] = e >= 0 ? w[j][s] : 0.0;
     }
   }
+  build_edge_tiles(g);
   return DC_OK;
 }
 

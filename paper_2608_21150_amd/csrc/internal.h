@@ -39,6 +39,14 @@ struct HostGrid {
   std::vector<double> k_curl;                     // [6][vs] (0 in pentagon slot 5)
   std::vector<double> k_lsq;                      // [18][vs] row j*6+s: component j, slot s
   std::vector<double> vert;                       // vertical tables, see VertTab
+  // tiles of the fused edge pass (see EdgeTiles below), tile-major so that a
+  // block reads its rows contiguously: counts [ntile][4] (own, vt set,
+  // staged set, vertices), staged edge ids [ntile][XM], local stencil
+  // positions [ntile][4][XV], vertex ids [ntile][VM], local v2e positions
+  // [ntile][6][VM], local end-vertex ids [ntile][2][256]
+  int et_ok = 0, et_ntile = 0;
+  std::vector<int32_t> et_n, et_x, et_vx;
+  std::vector<uint16_t> et_nb, et_vl, et_ev;
   // optional schemes, built on first use by a state that asks for them
   std::vector<double> k_vt_rbf;                   // [5][es] RBF tangential-wind weights
   std::vector<double> k_miura;                    // [18][es] Miura upwind coefficients
@@ -57,7 +65,22 @@ enum VertTab {
   VT_COUNT
 };
 
+// Fused edge pass: a tile is kTileE consecutive edges; its block stages vn of
+// the tile, of the rhombus edges of the tile (R1), of their rhombus edges
+// (R2) and of the edges around the tile's vertices in LDS, and forms vt and
+// K_e on tile + R1 and the vorticity at the tile's vertices there.  The
+// staged sets of one tile must fit the fixed capacities below; grids whose
+// numbering scatters neighbours further (et_ok = 0) keep separate
+// vorticity/kinetic-energy and edge passes.
+struct EdgeTiles {
+  static constexpr int kTileE = 256;  // edges per tile (= threads per block)
+  static constexpr int XM = 768;      // staged edges per tile
+  static constexpr int XV = 512;      // edges with vt and K_e per tile
+  static constexpr int VM = 256;      // vertices per tile
+};
+
 int build_host_grid(const dc_grid_desc* desc, HostGrid* g, std::string* err);
+void build_edge_tiles(HostGrid* g);
 bool build_rbf_vt(HostGrid* g);
 void build_miura(HostGrid* g);
 void lsq_vertex_weights(const HostGrid& g, int v, double w[3][6]);

@@ -67,6 +67,14 @@ struct DevGrid {
   const double* fe;     // [es] Coriolis parameter (per state)
   const double* tau;    // [K+1] sponge rate (per state)
   const double* kmiura; // [18][es] Miura upwind coefficients (per state; null when off)
+  // tiles of the fused edge pass (et_ok = 0: separate vorticity pass)
+  int et_ok, et_ntile;
+  const int* et_n;        // [ntile][4] own, vt set, staged set, vertices
+  const int* et_x;        // [ntile][XM] staged edge ids
+  const int* et_vx;       // [ntile][VM] vertex ids
+  const unsigned short* et_nb;  // [ntile][4][XV] local positions of e2c2e
+  const unsigned short* et_vl;  // [ntile][6][VM] local positions of v2e
+  const unsigned short* et_ev;  // [ntile][2][256] local ids of the own edges' end vertices
 };
 
 // Launch geometry of a level-blocked stencil kernel.

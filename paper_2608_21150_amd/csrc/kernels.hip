@@ -137,7 +137,8 @@ namespace {
 
 template <typename B>
 void one(int id, const DevGrid& g, const typename B::Args& a, const Tile* T, hipStream_t s, Prof* prof) {
-  const bodies::Geom geo = bodies::geom_of(id, g, T);
+  const bodies::Geom geo = bodies::geom_of(id, g, T, sizeof(typename B::Real));
+  if (geo.nbx == 0) return;  // nothing to do (the vorticity pass of a fused grid)
   const bool rec = prof && prof->wants(id);
   if (rec) prof->mark(s, id);
   bodies::k_one<B><<<dim3(geo.nbx, geo.nby), geo.threads, geo.smem, s>>>(g, a);

@@ -52,7 +52,8 @@ class GridDesc(ctypes.Structure):
 
 class GridInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("n_cells", "n_edges", "n_verts", "n_lev", "cell_stride", "edge_stride", "vert_stride")]
+                ("n_cells", "n_edges", "n_verts", "n_lev", "cell_stride", "edge_stride", "vert_stride",
+                 "fused_edge_pass")]
 
 
 class Params(ctypes.Structure):

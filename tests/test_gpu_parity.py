@@ -359,3 +359,54 @@ def test_fuller_numerics_options_parity(opts):
     a.close()
     b.close()
     G.close()
+
+
+def _shuffle_edges(g0, seed):
+    """The same grid with its edges numbered in a random order: every
+    tile of 256 consecutive edges then reaches far beyond the fused edge
+    pass's LDS, so the separate vorticity pass runs."""
+    rng = np.random.default_rng(seed)
+    ne = g0["n_edges"]
+    perm = rng.permutation(ne)          # new edge i is old edge perm[i]
+    inv = np.empty(ne, dtype=np.int64)
+    inv[perm] = np.arange(ne)
+    g = dict(g0)
+    for k in ("e2c", "e2v", "edge_xyz", "edge_normal_xyz"):
+        g[k] = np.ascontiguousarray(g0[k][perm])
+    for k in ("edge_length", "dual_edge_length"):
+        g[k] = np.ascontiguousarray(g0[k][perm])
+    g["c2e"] = inv[g0["c2e"]].astype(g0["c2e"].dtype)
+    return g, perm
+
+
+def test_edge_pass_forms_agree_with_oracle():
+    """The fused edge pass (generator and curve numbering) and the separate
+    vorticity pass (a random edge numbering, whose tiles do not fit the
+    fused form's LDS) both match the oracle on the R2B3 jet with noise."""
+    g0 = make_grid(2, 3)
+    S, vert = initial_state(g0, 12, 20e3, seed=21, vn_sigma=1.0, jet_u0=30.0, n_bumps=5,
+                            bump_radius=1500e3)
+    dt, nsub, steps = 300.0, 3, 4
+    ref, _ = run_oracle(g0, vert, S, dt, nsub, steps)
+    G = D.Grid(g0, vert)
+    assert G.info["fused_edge_pass"] == 1
+    G.close()
+    out, _ = run_gpu(g0, vert, S, dt, nsub, steps)
+    for k in FIELDS:
+        assert rel_l2(out[k], ref[k]) <= 1e-11, ("fused", k)
+    gs, perm = _shuffle_edges(g0, 5)
+    Ss = dict(S)
+    Ss["vn"] = np.ascontiguousarray(S["vn"][:, perm])
+    G = D.Grid(gs, vert)
+    assert G.info["fused_edge_pass"] == 0
+    G.close()
+    refs, _ = run_oracle(gs, vert, Ss, dt, nsub, steps)
+    outs, _ = run_gpu(gs, vert, Ss, dt, nsub, steps)
+    for k in FIELDS:
+        assert rel_l2(outs[k], refs[k]) <= 1e-11, ("separate", k)
+    # the two numberings describe the same grid: same answer
+    assert rel_l2(outs["vn"][:, np.argsort(perm)], out["vn"]) <= 1e-11
+    for prec in ("mixed",):
+        a, _ = run_gpu(gs, vert, Ss, dt, nsub, steps, precision=prec)
+        b, _ = run_gpu(g0, vert, S, dt, nsub, steps, precision=prec)
+        assert rel_l2(a["vn"][:, np.argsort(perm)], b["vn"]) <= 1e-5
