@@ -551,6 +551,34 @@ __device__ __forceinline__ double col_tw(const R* gw, const double* vert, int K1
   return (double)(R(-0.5) * hs - (R)(w_k * dwdz));
 }
 
+// The same from the three edge terms already loaded.
+template <typename R>
+__device__ __forceinline__ double col_tw_g(const R g[3], const double* vert, int K1, double w_up, double w_k,
+                                           double w_dn, int k, R inv_area) {
+  const R hs = (g[0] + g[1] + g[2]) * inv_area;
+  const double dwdz = (w_up - w_dn) * vert[VT_IDZC2 * K1 + k];
+  return (double)(R(-0.5) * hs - (R)(w_k * dwdz));
+}
+
+// Memory inputs of one step of the predictor's forward sweep at full level
+// j: the level below (rho, theta_v, exner at j + 1, clamped at the bottom;
+// w at half level j + 1), vn* at the cell's edges, the neighbours' rho and
+// theta_v (with the Miura option the edge values) and the edge terms of T_w
+// at half level j (ws and tw0 are the corrector's and stay unused).  A wave
+// loads the next level's inputs before it computes the current one, so the
+// memory latency of a level overlaps the previous level's arithmetic
+// (column_pred -7 % in FP64, -15 % mixed on R2B8).  The corrector keeps its
+// loads where they are used: its registers are full, and the same prefetch
+// spilled there and made it slower.
+template <typename R>
+struct LevIn {
+  double rho, th, ex, w, ws;
+  R vq[3];
+  double rn[3], tn[3];
+  R gq[3];
+  R tw0;
+};
+
 // State of one level of a column: full level j and half level j.
 struct ColLev {
   double rho, th, ex, thp, exp_;  // full level j
@@ -679,132 +707,296 @@ struct BCol {
     sv_t[0] = cur.th;
     sv_e[0] = cur.ex;
     double beta_p = 0.0, e_p = 0.0, atil_p = 0.0;
-  #pragma unroll
-    for (int i = 0; i <= LM; ++i) {
-      if (i <= n) {
-        const int j = h + i;
-        // the level below, clamped at the bottom (no branch: the last full
-        // level takes its own values and then overrides them)
-        const bool bottom = j + 1 >= K;
-        const int jn = bottom ? K - 1 : j + 1;
-        ColLev nx;
-        col_load(prho, pth, pex, vert, K1, cs, jn, c, nx);
-        col_half(vert, K1, cur, nx, jn, dtau, cpd, eta);
-        nx.w = pw[(size_t)(j + 1) * cs + c];
-        nx.ws = CORR ? pws[(size_t)(j + 1) * cs + c] : 0.0;
-        if (bottom) {
-          nx.ric = cur.rho;
-          nx.atil = 0.0;
-          nx.ws = 0.0;
-        }
-        sv_r[i + 1] = nx.rho;
-        sv_t[i + 1] = nx.th;
-        sv_e[i + 1] = nx.ex;
-        // mass and theta fluxes, explicit parts at full level j.  Neighbour
-        // rho, theta_v: the corrector takes those inside the 64-column tile
-        // from the other lanes' rows through LDS, the others from memory;
-        // the predictor reads them all from memory (the tile's rows were
-        // just read by the other lanes, so mostly from cache), which measured
-        // faster there
-        double dm = 0.0, dth = 0.0;
-        {
-          const R* vr = pvn + (size_t)j * g.es;
-          const double* rr = prho + (size_t)j * cs;
-          const double* tr = pth + (size_t)j * cs;
-          if (CORR) {
-            s_stg[p][0][cl] = cur.rho;
-            s_stg[p][1][cl] = cur.th;
-            __builtin_amdgcn_wave_barrier();
+    if constexpr (CORR) {
+    #pragma unroll
+      for (int i = 0; i <= LM; ++i) {
+        if (i <= n) {
+          const int j = h + i;
+          // the level below, clamped at the bottom (no branch: the last full
+          // level takes its own values and then overrides them)
+          const bool bottom = j + 1 >= K;
+          const int jn = bottom ? K - 1 : j + 1;
+          ColLev nx;
+          col_load(prho, pth, pex, vert, K1, cs, jn, c, nx);
+          col_half(vert, K1, cur, nx, jn, dtau, cpd, eta);
+          nx.w = pw[(size_t)(j + 1) * cs + c];
+          nx.ws = CORR ? pws[(size_t)(j + 1) * cs + c] : 0.0;
+          if (bottom) {
+            nx.ric = cur.rho;
+            nx.atil = 0.0;
+            nx.ws = 0.0;
           }
-          R vq[3];
-          if (cf.miura) {
-            // Miura edge values stored by the upwind pass
-            const double* er = prhoe + (size_t)j * g.es;
-            const double* et = pthe + (size_t)j * g.es;
-  #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-              vq[q] = vr[ie[q]];
-              const double fm = er[ie[q]] * (double)vq[q];
-              dm += kd[q] * fm;
-              dth += kd[q] * (fm * et[ie[q]]);
+          sv_r[i + 1] = nx.rho;
+          sv_t[i + 1] = nx.th;
+          sv_e[i + 1] = nx.ex;
+          // mass and theta fluxes, explicit parts at full level j.  Neighbour
+          // rho, theta_v: the corrector takes those inside the 64-column tile
+          // from the other lanes' rows through LDS, the others from memory;
+          // the predictor reads them all from memory (the tile's rows were
+          // just read by the other lanes, so mostly from cache), which measured
+          // faster there
+          double dm = 0.0, dth = 0.0;
+          {
+            const R* vr = pvn + (size_t)j * g.es;
+            const double* rr = prho + (size_t)j * cs;
+            const double* tr = pth + (size_t)j * cs;
+            if (CORR) {
+              s_stg[p][0][cl] = cur.rho;
+              s_stg[p][1][cl] = cur.th;
+              __builtin_amdgcn_wave_barrier();
             }
-          } else {
+            R vq[3];
+            if (cf.miura) {
+              // Miura edge values stored by the upwind pass
+              const double* er = prhoe + (size_t)j * g.es;
+              const double* et = pthe + (size_t)j * g.es;
+    #pragma unroll
+              for (int q = 0; q < 3; ++q) {
+                vq[q] = vr[ie[q]];
+                const double fm = er[ie[q]] * (double)vq[q];
+                dm += kd[q] * fm;
+                dth += kd[q] * (fm * et[ie[q]]);
+              }
+            } else {
+      #pragma unroll
+              for (int q = 0; q < 3; ++q) {
+                vq[q] = vr[ie[q]];
+                double rn, tn;
+                if (CORR) {
+                  // the LDS read is unconditional (masked index), the memory
+                  // read only for neighbours outside the tile (written as
+                  // selects: an if-statement form makes the gfx950 backend fail
+                  // machine verification)
+                  const int lq = nb[q] - bx * 64;
+                  rn = s_stg[p][0][lq & 63];
+                  tn = s_stg[p][1][lq & 63];
+                  rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
+                  tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
+                } else {
+                  rn = rr[nb[q]];
+                  tn = tr[nb[q]];
+                }
+                // edge means and fluxes in FP64 in both forms (mixed: from the
+                // FP32 vn): an FP32 rounding of the fluxes would add to the
+                // divergence errors that drive w and rho
+                const double rho_e = 0.5 * (cur.rho + rn);
+                const double th_e = 0.5 * (cur.th + tn);
+                const double fm = rho_e * (double)vq[q];
+                const double ft = fm * th_e;
+                dm += kd[q] * fm;
+                dth += kd[q] * ft;
+              }
+            }
+            if (CORR) __builtin_amdgcn_wave_barrier();
+            // predictor: divergence of vn* for the corrector's damping (each
+            // full level is stored by the chunk that owns it)
+            // (level h of chunk p > 0 is also stored by chunk p - 1: the same value)
+            if (!CORR) pdv[(size_t)j * cs + c0] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
+          }
+          const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
+          const double beta = b * idzf[j];
+          const double drx = -dtau * (dm + oneme * (cur.ric * cur.w - nx.ric * nx.w) * idzf[j]);
+          const double dxx = -b * (dth + oneme * (cur.atil * cur.w - nx.atil * nx.w) * idzf[j]);
+          const double e_c = cur.exp_ + dxx;
+          drxv[i] = drx;
+          dxxv[i] = dxx;
+          if (i >= 1) {
+            // row of half level j, then one step of the down sweep
+            double tw;
+            if (CORR) {
+              tw = cf.a0 * (double)ptw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(pgw, vert, K1, g.es, ws_up, cur.ws, nx.ws, j, ie, inv_area);
+            } else {
+              tw = col_tw<R>(pgw, vert, K1, g.es, w_up, cur.w, nx.w, j, ie, inv_area);
+              ptw0[(size_t)j * cs + c0] = (R)tw;
+            }
+            const double wx = cur.w + dtau * (tw - cpd * cur.zth);
+            const double A = -cur.gam * beta_p * (eta * atil_p);
+            const double B = 1.0 + cur.gam * (eta * cur.atil) * (beta_p + beta);
+            const double C = -cur.gam * beta * (eta * nx.atil);
+            const double rhs = wx - cur.gam * (e_p - e_c);
+            // one reciprocal per row: the pivots are >= 1, so multiplying by
+            // it loses nothing against three divisions
+            if (i == 1) {
+              const double r = 1.0 / B;
+              cpv[0] = C * r;
+              dpv[0] = rhs * r;
+              lpv[0] = A * r;
+            } else {
+              const double r = 1.0 / (B - A * cpv[i - 2]);
+              cpv[i - 1] = C * r;
+              dpv[i - 1] = (rhs - A * dpv[i - 2]) * r;
+              lpv[i - 1] = -A * lpv[i - 2] * r;
+            }
+          }
+          beta_p = beta;
+          e_p = e_c;
+          atil_p = cur.atil;
+          w_up = cur.w;
+          ws_up = cur.ws;
+          cur = nx;
+        }
+      }
+    } else {
+      // the predictor loads the next level's inputs before it computes
+      // the current level (see LevIn)
+      auto load_in = [&](int j, LevIn<R>& L) {
+        const int jn = j + 1 >= K ? K - 1 : j + 1;
+        const size_t r = (size_t)jn * cs + c;
+        L.rho = prho[r];
+        L.th = pth[r];
+        L.ex = pex[r];
+        L.w = pw[(size_t)(j + 1) * cs + c];
+        L.ws = CORR ? pws[(size_t)(j + 1) * cs + c] : 0.0;
+        const R* vr = pvn + (size_t)j * g.es;
+        const R* gr = pgw + (size_t)j * g.es;
+    #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          L.vq[q] = vr[ie[q]];
+          L.gq[q] = gr[ie[q]];
+        }
+        if (cf.miura) {
+    #pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            L.rn[q] = prhoe[(size_t)j * g.es + ie[q]];
+            L.tn[q] = pthe[(size_t)j * g.es + ie[q]];
+          }
+        } else if (!CORR) {
+    #pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            L.rn[q] = prho[(size_t)j * cs + nb[q]];
+            L.tn[q] = pth[(size_t)j * cs + nb[q]];
+          }
+        }
+        L.tw0 = CORR ? ptw0[(size_t)j * cs + c] : R(0);
+      };
+      LevIn<R> in_a;
+      load_in(h, in_a);
+    #pragma unroll
+      for (int i = 0; i <= LM; ++i) {
+        if (i <= n) {
+          const int j = h + i;
+          LevIn<R> in_b = in_a;
+          if (i + 1 <= n) load_in(j + 1, in_b);
+          // the level below, clamped at the bottom (no branch: the last full
+          // level takes its own values and then overrides them)
+          const bool bottom = j + 1 >= K;
+          const int jn = bottom ? K - 1 : j + 1;
+          ColLev nx;
+          nx.rho = in_a.rho;
+          nx.th = in_a.th;
+          nx.ex = in_a.ex;
+          nx.thp = nx.th - vert[VT_THREF * K1 + jn];
+          nx.exp_ = nx.ex - vert[VT_EXREF * K1 + jn];
+          col_half(vert, K1, cur, nx, jn, dtau, cpd, eta);
+          nx.w = in_a.w;
+          nx.ws = in_a.ws;
+          if (bottom) {
+            nx.ric = cur.rho;
+            nx.atil = 0.0;
+            nx.ws = 0.0;
+          }
+          sv_r[i + 1] = nx.rho;
+          sv_t[i + 1] = nx.th;
+          sv_e[i + 1] = nx.ex;
+          // mass and theta fluxes, explicit parts at full level j.  Neighbour
+          // rho, theta_v: the corrector takes those inside the 64-column tile
+          // from the other lanes' rows through LDS, the others from memory;
+          // the predictor reads them all from memory (the tile's rows were
+          // just read by the other lanes, so mostly from cache), which measured
+          // faster there
+          double dm = 0.0, dth = 0.0;
+          {
+            const double* rr = prho + (size_t)j * cs;
+            const double* tr = pth + (size_t)j * cs;
+            if (CORR) {
+              s_stg[p][0][cl] = cur.rho;
+              s_stg[p][1][cl] = cur.th;
+              __builtin_amdgcn_wave_barrier();
+            }
+            const R* vq = in_a.vq;
     #pragma unroll
             for (int q = 0; q < 3; ++q) {
-              vq[q] = vr[ie[q]];
-              double rn, tn;
-              if (CORR) {
-                // the LDS read is unconditional (masked index), the memory
-                // read only for neighbours outside the tile (written as
-                // selects: an if-statement form makes the gfx950 backend fail
-                // machine verification)
-                const int lq = nb[q] - bx * 64;
-                rn = s_stg[p][0][lq & 63];
-                tn = s_stg[p][1][lq & 63];
-                rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
-                tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
+              double rho_e, th_e;
+              if (cf.miura) {
+                // Miura edge values stored by the upwind pass
+                rho_e = in_a.rn[q];
+                th_e = in_a.tn[q];
               } else {
-                rn = rr[nb[q]];
-                tn = tr[nb[q]];
+                double rn, tn;
+                if (CORR) {
+                  // the LDS read is unconditional (masked index), the memory
+                  // read only for neighbours outside the tile (written as
+                  // selects: an if-statement form makes the gfx950 backend
+                  // fail machine verification)
+                  const int lq = nb[q] - bx * 64;
+                  rn = s_stg[p][0][lq & 63];
+                  tn = s_stg[p][1][lq & 63];
+                  rn = (unsigned)lq >= 64u ? rr[nb[q]] : rn;
+                  tn = (unsigned)lq >= 64u ? tr[nb[q]] : tn;
+                } else {
+                  rn = in_a.rn[q];
+                  tn = in_a.tn[q];
+                }
+                rho_e = 0.5 * (cur.rho + rn);
+                th_e = 0.5 * (cur.th + tn);
               }
               // edge means and fluxes in FP64 in both forms (mixed: from the
               // FP32 vn): an FP32 rounding of the fluxes would add to the
               // divergence errors that drive w and rho
-              const double rho_e = 0.5 * (cur.rho + rn);
-              const double th_e = 0.5 * (cur.th + tn);
               const double fm = rho_e * (double)vq[q];
               const double ft = fm * th_e;
               dm += kd[q] * fm;
               dth += kd[q] * ft;
             }
+            if (CORR) __builtin_amdgcn_wave_barrier();
+            // predictor: divergence of vn* for the corrector's damping (each
+            // full level is stored by the chunk that owns it)
+            // (level h of chunk p > 0 is also stored by chunk p - 1: the same value)
+            if (!CORR) pdv[(size_t)j * cs + c0] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
           }
-          if (CORR) __builtin_amdgcn_wave_barrier();
-          // predictor: divergence of vn* for the corrector's damping (each
-          // full level is stored by the chunk that owns it)
-          // (level h of chunk p > 0 is also stored by chunk p - 1: the same value)
-          if (!CORR) pdv[(size_t)j * cs + c0] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
+          const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
+          const double beta = b * idzf[j];
+          const double drx = -dtau * (dm + oneme * (cur.ric * cur.w - nx.ric * nx.w) * idzf[j]);
+          const double dxx = -b * (dth + oneme * (cur.atil * cur.w - nx.atil * nx.w) * idzf[j]);
+          const double e_c = cur.exp_ + dxx;
+          drxv[i] = drx;
+          dxxv[i] = dxx;
+          if (i >= 1) {
+            // row of half level j, then one step of the down sweep
+            double tw;
+            if (CORR) {
+              tw = cf.a0 * (double)in_a.tw0 + cf.a1 * col_tw_g<R>(in_a.gq, vert, K1, ws_up, cur.ws, nx.ws, j, inv_area);
+            } else {
+              tw = col_tw_g<R>(in_a.gq, vert, K1, w_up, cur.w, nx.w, j, inv_area);
+              ptw0[(size_t)j * cs + c0] = (R)tw;
+            }
+            const double wx = cur.w + dtau * (tw - cpd * cur.zth);
+            const double A = -cur.gam * beta_p * (eta * atil_p);
+            const double B = 1.0 + cur.gam * (eta * cur.atil) * (beta_p + beta);
+            const double C = -cur.gam * beta * (eta * nx.atil);
+            const double rhs = wx - cur.gam * (e_p - e_c);
+            // one reciprocal per row: the pivots are >= 1, so multiplying by
+            // it loses nothing against three divisions
+            if (i == 1) {
+              const double r = 1.0 / B;
+              cpv[0] = C * r;
+              dpv[0] = rhs * r;
+              lpv[0] = A * r;
+            } else {
+              const double r = 1.0 / (B - A * cpv[i - 2]);
+              cpv[i - 1] = C * r;
+              dpv[i - 1] = (rhs - A * dpv[i - 2]) * r;
+              lpv[i - 1] = -A * lpv[i - 2] * r;
+            }
+          }
+          beta_p = beta;
+          e_p = e_c;
+          atil_p = cur.atil;
+          w_up = cur.w;
+          ws_up = cur.ws;
+          cur = nx;
+          in_a = in_b;
         }
-        const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
-        const double beta = b * idzf[j];
-        const double drx = -dtau * (dm + oneme * (cur.ric * cur.w - nx.ric * nx.w) * idzf[j]);
-        const double dxx = -b * (dth + oneme * (cur.atil * cur.w - nx.atil * nx.w) * idzf[j]);
-        const double e_c = cur.exp_ + dxx;
-        drxv[i] = drx;
-        dxxv[i] = dxx;
-        if (i >= 1) {
-          // row of half level j, then one step of the down sweep
-          double tw;
-          if (CORR) {
-            tw = cf.a0 * (double)ptw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(pgw, vert, K1, g.es, ws_up, cur.ws, nx.ws, j, ie, inv_area);
-          } else {
-            tw = col_tw<R>(pgw, vert, K1, g.es, w_up, cur.w, nx.w, j, ie, inv_area);
-            ptw0[(size_t)j * cs + c0] = (R)tw;
-          }
-          const double wx = cur.w + dtau * (tw - cpd * cur.zth);
-          const double A = -cur.gam * beta_p * (eta * atil_p);
-          const double B = 1.0 + cur.gam * (eta * cur.atil) * (beta_p + beta);
-          const double C = -cur.gam * beta * (eta * nx.atil);
-          const double rhs = wx - cur.gam * (e_p - e_c);
-          // one reciprocal per row: the pivots are >= 1, so multiplying by
-          // it loses nothing against three divisions
-          if (i == 1) {
-            const double r = 1.0 / B;
-            cpv[0] = C * r;
-            dpv[0] = rhs * r;
-            lpv[0] = A * r;
-          } else {
-            const double r = 1.0 / (B - A * cpv[i - 2]);
-            cpv[i - 1] = C * r;
-            dpv[i - 1] = (rhs - A * dpv[i - 2]) * r;
-            lpv[i - 1] = -A * lpv[i - 2] * r;
-          }
-        }
-        beta_p = beta;
-        e_p = e_c;
-        atil_p = cur.atil;
-        w_up = cur.w;
-        ws_up = cur.ws;
-        cur = nx;
       }
     }
     // ---- up sweep: row i of the chunk = d_i - u_i x_below - v_i x_above ----
