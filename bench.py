@@ -42,19 +42,20 @@ def kernel_bytes(C, E, V, K, r):
     reads or writes counted once per (entity, level); r = bytes of vn and of
     the horizontal intermediates (8 FP64, 4 mixed); cell prognostics are 8.
     gw is the edge term of the horizontal advection of w ([K+1][E], r bytes),
-    tw0 the substep-start T_w ([K+1][C], r bytes)."""
+    tw0 the substep-start T_w ([K+1][C], r bytes).  The edge passes are the
+    fused ones (a grid numbered with locality): vt, K_e and the vorticity
+    stay in LDS, the vorticity pass is not launched and the corrector's cell
+    pass forms only the damping field D2."""
     KE, KV, KC, K1C, K1E = K * E, K * V, K * C, (K + 1) * C, (K + 1) * E
     return {
-        # reads vn; writes vt, K_e (edges), zeta (vertices)
-        "vort_ke_pred": r * KE + 2 * r * KE + r * KV,
-        # reads vn, zeta, K_e, vt, w, exner, theta; writes Y = vn + dtau (a0 T_vn0 - PGF), vn*, gw
-        "edge_pred": r * KE + r * KV + 2 * r * KE + 8 * K1C + 8 * 2 * KC + r * 3 * KE,
+        # reads vn, w, exner, theta; writes Y = vn + dtau (a0 T_vn0 - PGF), vn*, gw
+        "edge_pred": r * KE + 8 * K1C + 8 * 2 * KC + r * 3 * KE,
         # reads gw, vn*, w, rho, exner, theta; writes w*, tw0, D = div vn*
         "column_pred": r * K1E + r * KE + 8 * K1C + 8 * 3 * KC + 8 * K1C + r * K1C + r * KC,
-        # reads vn*, D; writes vt, K_e, zeta, D2
-        "vort_ke_corr": 3 * r * KE + r * KV + 2 * r * KC,
-        # reads vn*, Y, zeta, K_e, vt, D2, w*; writes vn', gw
-        "edge_corr": r * 2 * KE + r * KV + 2 * r * KE + r * KC + 8 * K1C + r * 2 * KE,
+        # reads D; writes D2
+        "vort_ke_corr": 2 * r * KC,
+        # reads vn*, Y, D2, w*; writes vn', gw
+        "edge_corr": r * 2 * KE + r * KC + 8 * K1C + r * 2 * KE,
         # reads gw, vn', w, w*, tw0, rho, exner, theta; writes w, rho, exner, theta
         "column_corr": r * K1E + r * KE + 8 * 2 * K1C + r * K1C + 8 * 3 * KC + 8 * (K1C + 3 * KC),
         "diff_vertex": r * KE + r * 4 * KV,
