@@ -302,17 +302,45 @@ struct BEdge {
     return o;
   }
 
+  // Cell and edge values of the momentum update at level j: the predictor's
+  // exner and theta_v at c0, c1 (with the Miura option theta_v at the edge
+  // in t0), the corrector's damping field at c0, c1 and its stored Y.
+  struct EdgeIn {
+    double x0, x1, t0, t1;
+    R d0, d1, y;
+  };
+  __device__ __forceinline__ static EdgeIn edge_in(const DevGrid& g, const StepCoef& cf, const Own& o, int j,
+                                                   const double* __restrict__ ex, const double* __restrict__ th,
+                                                   const double* __restrict__ the_m, const R* __restrict__ d2,
+                                                   const R* __restrict__ tvn0) {
+    EdgeIn v{};
+    const size_t rc = (size_t)j * g.cs, re = (size_t)j * g.es + o.e;
+    if (!CORR) {
+      v.x0 = ex[rc + o.c0];
+      v.x1 = ex[rc + o.c1];
+      if (cf.miura) {
+        v.t0 = the_m[re];
+      } else {
+        v.t0 = th[rc + o.c0];
+        v.t1 = th[rc + o.c1];
+      }
+    } else {
+      v.d0 = d2[rc + o.c0];
+      v.d1 = d2[rc + o.c1];
+      v.y = tvn0[re];
+    }
+    return v;
+  }
+
   // The edge's work at full level j from vn at j - 1, j, j + 1, w at c0, c1
   // on half levels j and j + 1, the vorticity at the edge, the K_e of its
-  // four rhombus edges and its vt.
+  // four rhombus edges, its vt and the values of edge_in.
   // The fields are restrict parameters: no buffer is both read and written
   // by one launch, so loads of later levels may move above earlier stores.
   __device__ __forceinline__ static void level(const DevGrid& g, const StepCoef& cf, const Own& o, int j, R vup,
                                                R vj, R vdn, double wa0, double wa1, double wb0, double wb1, R ze,
-                                               const R kq[4], R vt, R* __restrict__ gw, R* __restrict__ tvn0,
-                                               R* __restrict__ vout, const double* __restrict__ ex,
-                                               const double* __restrict__ th, const double* __restrict__ the_m,
-                                               const R* __restrict__ d2) {
+                                               const R kq[4], R vt, const EdgeIn& in_v, R* __restrict__ gw,
+                                               R* __restrict__ tvn0, R* __restrict__ vout) {
     const int K = g.K;
     const size_t re = (size_t)j * g.es + o.e;
     const R ie_top = j > 0 ? R(0.5) * (vup + vj) : vj;
@@ -325,7 +353,6 @@ struct BEdge {
     // both neighbouring cells take l_e vn_ie (w_c1 - w_c0) / A_c
     if (j > 0 && o.in) gw[re] = o.le * ie_top * (R)(wa1 - wa0);
     const R tvn = (ze + o.fe) * vt - kgrad - wef * (ie_top - ie_bot) * (R)vt_row(g, VT_IDZF)[j];
-    const size_t rc = (size_t)j * g.cs;
     if (!CORR) {
       // the pressure-gradient term comes from the substep's start state in
       // both passes: the predictor forms it once and stores the start vn
@@ -333,16 +360,16 @@ struct BEdge {
       // vn + dtau (a0 T_vn0 - cpd theta_e grad pi'), which is all the
       // corrector needs of the three
       const double exr = vt_row(g, VT_EXREF)[j];
-      const R gex = (R)((ex[rc + o.c1] - exr) - (ex[rc + o.c0] - exr)) * o.invd_r;
-      const R the = cf.miura ? (R)the_m[re] : (R)(0.5 * (th[rc + o.c0] + th[rc + o.c1]));
+      const R gex = (R)((in_v.x1 - exr) - (in_v.x0 - exr)) * o.invd_r;
+      const R the = cf.miura ? (R)in_v.t0 : (R)(0.5 * (in_v.t0 + in_v.t1));
       const R pgf = (R)cf.cpd * the * gex;
       if (o.in) {
         tvn0[re] = vj + (R)cf.dtau * ((R)cf.a0 * tvn - pgf);
         vout[re] = vj + (R)cf.dtau * (tvn - pgf);
       }
     } else {
-      const R dd = (d2[rc + o.c1] - d2[rc + o.c0]) * o.invd_r;
-      if (o.in) vout[re] = tvn0[re] + ((R)cf.dtau * (R)cf.a1 * tvn - (R)cf.c4a2 * dd);
+      const R dd = (in_v.d1 - in_v.d0) * o.invd_r;
+      if (o.in) vout[re] = in_v.y + ((R)cf.dtau * (R)cf.a1 * tvn - (R)cf.c4a2 * dd);
     }
   }
 
@@ -426,6 +453,7 @@ struct BEdge {
       const size_t re = (size_t)j * g.es + o.e;
       const R vdn = j < K - 1 ? vn[re + g.es] : vn[re];
       const double wb0 = w[(size_t)(j + 1) * g.cs + o.c0], wb1 = w[(size_t)(j + 1) * g.cs + o.c1];
+      const EdgeIn in_v = edge_in(g, args.cf, o, j, args.ex, args.th, args.the, args.d2, args.tvn0);
       __syncthreads();
   #pragma unroll
       for (int q = 0; q < 2; ++q)
@@ -450,8 +478,7 @@ struct BEdge {
       R kq[4];
   #pragma unroll
       for (int q = 0; q < 4; ++q) kq[q] = ske[nbl[0][q]];
-      level(g, args.cf, o, j, vup, vj, vdn, wa0, wa1, wb0, wb1, ze, kq, svt[tid], args.gw, args.tvn0, args.vout, args.ex,
-            args.th, args.the, args.d2);
+      level(g, args.cf, o, j, vup, vj, vdn, wa0, wa1, wb0, wb1, ze, kq, svt[tid], in_v, args.gw, args.tvn0, args.vout);
       vup = vj;
       wa0 = wb0;
       wa1 = wb1;
@@ -499,8 +526,8 @@ struct BEdge {
         const R x = s_ke[j & 1][l & (kThreads - 1)];
         kq[q] = (unsigned)l < (unsigned)blockDim.x ? x : kr[rh[q]];
       }
-      level(g, args.cf, o, j, vup, vj, vdn, wa0, wa1, wb0, wb1, ze, kq, vtf[re], args.gw, args.tvn0, args.vout,
-            args.ex, args.th, args.the, args.d2);
+      const EdgeIn in_v = edge_in(g, args.cf, o, j, args.ex, args.th, args.the, args.d2, args.tvn0);
+      level(g, args.cf, o, j, vup, vj, vdn, wa0, wa1, wb0, wb1, ze, kq, vtf[re], in_v, args.gw, args.tvn0, args.vout);
       vup = vj;
       vj = vdn;
       wa0 = wb0;
