@@ -390,7 +390,44 @@ def bench_ensemble(args, D, torch):
         st.close()
     for _, G in grids.values():
         G.close()
+    line["small_members"] = bench_ensemble_small(args, D, torch, timed)
     print(json.dumps(line), flush=True)
+
+
+def bench_ensemble_small(args, D, torch, timed, n_members=64):
+    """Where batching pays: many small members (R2B2, 30 levels, mixed), whose
+    per-member launches are short enough that the launch cost of a loop over
+    them shows (the paper's Section 4.3.3 hides it behind asynchronous
+    dispatch); one graph launch per step against the per-member loop."""
+    from synth import initial_state, make_grid
+
+    g = make_grid(2, 2)
+    _, vert = initial_state(g, 30, 30e3, seed=0)
+    G = D.Grid(g, vert)
+    states = []
+    for m in range(n_members):
+        S, _ = initial_state(g, 30, 30e3, seed=2000 + m, vn_sigma=1.0, t_sigma=0.2, jet_u0=35.0)
+        st = D.State(G, precision="mixed")
+        st.write(S)
+        states.append(st)
+    dt, nsub = 600.0, 5
+    E = D.Ensemble(states)
+    ms_graph = timed(lambda: E.step(dt, nsub), args.steps)
+    E.close()
+
+    def loop():
+        for st in states:
+            st.step(dt, nsub)
+
+    ms_loop = timed(loop, args.steps)
+    for st in states:
+        st.close()
+    G.close()
+    cells = n_members * g["n_cells"] * 30
+    return {"members": n_members, "workload": "R2B2 (1280 cells), 30 levels, mixed, dt 600 s, 5 substeps, "
+                                              "default schedule",
+            "ms_per_step": ms_graph, "value": cells / (ms_graph * 1e-3),
+            "per_member_loop_ms_per_step": ms_loop, "speedup_vs_loop": ms_loop / ms_graph}
 
 
 def bench_surrogate(args, D, torch):
