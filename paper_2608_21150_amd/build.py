@@ -27,6 +27,10 @@ HIP_FLAGS = [
 # host grid layer: no FP contraction so floating-point decisions are taken as written
 CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-ffp-contract=off", "-I", INCLUDE, "-I", CSRC]
 
+# per-source extra flags: the network kernels keep MFMA results in ordinary
+# VGPRs (no accumulator-register copies before the activations read them)
+EXTRA_FLAGS = {"mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 SOURCES = [
     ("grid.cpp", "cxx"),
     ("abi.hip", "hip"),
@@ -52,7 +56,7 @@ def build(verbose: bool = False) -> str:
             continue
         obj = os.path.join(BUILD, name + ".o")
         if kind == "hip":
-            cmd = [HIPCC, *HIP_FLAGS, "-c", src, "-o", obj]
+            cmd = [HIPCC, *HIP_FLAGS, *EXTRA_FLAGS.get(name, []), "-c", src, "-o", obj]
         else:
             cmd = [shutil.which("g++") or "g++", *CXX_FLAGS, "-c", src, "-o", obj]
         jobs.append((cmd, obj))

@@ -1,6 +1,9 @@
 // Learned stand-in for the vn diffusion step: an 18 -> 64 -> 64 -> 1
-// perceptron with exact (erf) GELU, BF16 operands on the matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation) and FP32 master weights.
+// perceptron with GELU, BF16 operands on the matrix cores (FP32
+// accumulation) and FP32 master weights.  Training (forward, backward) uses
+// v_mfma_f32_16x16x16_bf16 and the erf form of GELU; inference uses
+// v_mfma_f32_16x16x32_bf16 in the transposed orientation described at
+// forward_t and a polynomial GELU within 4.6e-5 of the erf form.
 // The paper motivates coupling the dynamical core to machine-learning
 // workflows (Sections 3 and 6); the features, the network, its training and
 // the per-column fallback to the plain diffusion are readings of this
@@ -70,11 +73,6 @@ __device__ __forceinline__ void normal_cdf_pdf(float x, float& cdf, float& pdf) 
   pdf = e * 0.39894228040143268f;
 }
 // exact-erf GELU x Phi(x) and its derivative Phi(x) + x phi(x)
-__device__ __forceinline__ float gelu(float x) {
-  float c, d;
-  normal_cdf_pdf(x, c, d);
-  return x * c;
-}
 __device__ __forceinline__ void gelu_and_grad(float x, float& g, float& gd) {
   float c, d;
   normal_cdf_pdf(x, c, d);
@@ -140,39 +138,118 @@ __device__ void stage_weights(SW& s, const float* __restrict__ p, bf16* w2n) {
   if (threadIdx.x == 0) s.b3 = p[OFF_B3];
 }
 
-// Forward of the wave's 64 samples (normalised BF16 features in xs), one
-// 16-row tile at a time; y[st][t] receives the output of row 16 st + 4 q + t
-// (all 16 lanes of a row group hold it).  hs is the wave's 16-row h1 tile.
-// Uses only the wave's own LDS rows.
-__device__ void forward64(const SW& s, const bf16* xs, bf16* hs, float y[4][4]) {
-  const int l = threadIdx.x & 63, j = l & 15, q = l >> 4;
+// ---------------------------------------------------------------------------
+// Inference forward (no gradients) in the transposed orientation: hidden
+// units are the rows and samples the columns of every product, so that a
+// layer-1 result tile is already the B operand of layer 2 and activations
+// never pass through LDS.  v_mfma_f32_16x16x32_bf16: lane l = 16 q + j holds
+// row j of A and column j of B, eight k slots each, and receives rows
+// 4q..4q+3 of column j.  Any map of (q, slot) to k serves when A and B share
+// it: layer 1 takes feature 8q + slot; layer 2's k step m takes hidden units
+// 32m + 4q + slot (slot < 4) and 32m + 16 + 4q + slot - 4 (slot >= 4), which
+// are exactly the outputs of layer-1 tiles 2m and 2m+1 in the same lane.  The
+// weight fragments, biases (the accumulators' initial values) and w3 stay in
+// registers for the whole kernel.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+// GELU(x) = x Phi(x) with Phi(x) = 1/2 + x Q(x^2): Q is a degree-8 polynomial
+// in s = min(x^2, T^2) (T = 4.25) and Phi is clamped to [0, 1]; largest
+// deviation from the erf form 4.6e-5 (at |x| = T; 1.7e-5 for |x| < 3.5),
+// below the BF16 resolution of the activations.  The coefficients are
+// printed by gelu_fit.py beside this package's sources.
+constexpr float kGeluT2 = 18.0625f;
+constexpr float kGeluQ[9] = {3.988192976e-01f, -6.619048119e-02f, 9.718909860e-03f, -1.079113572e-03f,
+                             8.849387086e-05f, -5.147835964e-06f, 1.986260969e-07f, -4.515380070e-09f,
+                             4.546895846e-11f};
+__device__ __forceinline__ float gelu_poly(float x) {
+  const float s = fminf(x * x, kGeluT2);
+  float a = kGeluQ[8];
 #pragma unroll
-  for (int st = 0; st < 4; ++st) {
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) acc = mfma(frag(xs, XS, 16 * st, 16 * ks), frag(s.w1t, XS, 16 * nt, 16 * ks), acc);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) hs[(4 * q + t) * HS + 16 * nt + j] = to_bf16(gelu(acc[t] + s.b1[16 * nt + j]));
-    }
-    wave_lds_sync();
-    float yp[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) acc = mfma(frag(hs, HS, 0, 16 * ks), frag(s.w2t, HS, 16 * nt, 16 * ks), acc);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) yp[t] += gelu(acc[t] + s.b2[16 * nt + j]) * s.w3[16 * nt + j];
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) y[st][t] = sum16(yp[t]) + s.b3;
-    wave_lds_sync();
-  }
+  for (int i = 7; i >= 0; --i) a = fmaf(a, s, kGeluQ[i]);
+  return x * __builtin_amdgcn_fmed3f(fmaf(x, a, 0.5f), 0.0f, 1.0f);
 }
 
-// The 18 raw features of edge e at level k, from vn, vt (edges), D = div vn
+__device__ __forceinline__ int l2_unit(int m, int q, int slot) { return 32 * m + 4 * q + (slot < 4 ? slot : 12 + slot); }
+
+struct RegNet {
+  bf8 w1[4];               // hidden tile nt: W1[8q + slot][16 nt + j]
+  bf8 w2[4][2];            // output tile nt, k step m: W2[l2_unit(m, q, slot)][16 nt + j]
+  f4 b1[4], b2[4], w3[4];  // unit 16 nt + 4 q + t
+  float b3;
+};
+
+__device__ void load_net(RegNet& n, const float* __restrict__ p) {
+  const int l = threadIdx.x & 63, j = l & 15, q = l >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      const int f = 8 * q + sl;
+      n.w1[nt][sl] = (__bf16)(f < NIN ? p[OFF_W1 + f * NH + 16 * nt + j] : 0.0f);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) n.w2[nt][m][sl] = (__bf16)p[OFF_W2 + l2_unit(m, q, sl) * NH + 16 * nt + j];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int u = 16 * nt + 4 * q + t;
+      n.b1[nt][t] = p[OFF_B1 + u];
+      n.b2[nt][t] = p[OFF_B2 + u];
+      n.w3[nt][t] = p[OFF_W3 + u];
+    }
+  }
+  n.b3 = p[OFF_B3];
+}
+
+// Output (normalised) of the wave's 64 samples: xs row r (stride XS) holds
+// sample r's normalised BF16 features in columns 0..31 (zero beyond NIN);
+// lane l returns sample l's output.  Reads only the wave's own LDS rows.
+__device__ float forward_t(const RegNet& n, const bf16* xs) {
+  const int l = threadIdx.x & 63, j = l & 15, q = l >> 4;
+  float y = 0.f;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const bf8 xb = *reinterpret_cast<const bf8*>(xs + (16 * st + j) * XS + 8 * q);
+    f4 a1[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) a1[nt] = mfma32(n.w1[nt], xb, n.b1[nt]);
+    bf8 hb[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        hb[m][t] = (__bf16)gelu_poly(a1[2 * m][t]);
+        hb[m][4 + t] = (__bf16)gelu_poly(a1[2 * m + 1][t]);
+      }
+    float yp = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f4 a2 = mfma32(n.w2[nt][0], hb[0], n.b2[nt]);
+      a2 = mfma32(n.w2[nt][1], hb[1], a2);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) yp = fmaf(gelu_poly(a2[t]), n.w3[nt][t], yp);
+    }
+    yp = sumq(yp);
+    if (q == st) y = yp;
+  }
+  return y + n.b3;
+}
+
+// Writes lane l's normalised BF16 feature row (columns 0..31) into xs row l.
+__device__ __forceinline__ void put_row(bf16* xs, const float* v) {
+  const int l = threadIdx.x & 63;
+  bf8 r[4];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) r[c >> 3][c & 7] = (__bf16)(c < NIN ? v[c] : 0.0f);
+  bf8* d = reinterpret_cast<bf8*>(xs + l * XS);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) d[c] = r[c];
+}
+
+// The 18 raw features of edge e at level k, from vn (edges; vt formed here
+// with the step's tangential-wind stencil), D = div vn
 // (cells), Z = curl vn (vertices), DL = div L1 (cells), CL = curl L1
 // (vertices) and the vertex vectors V (three component planes `plane`
 // apart); the fields are those of the plain diffusion.  Stencil values
@@ -182,7 +259,7 @@ __device__ void forward64(const SW& s, const bf16* xs, bf16* hs, float y[4][4]) 
 // div L1 at c0, c1; curl L1 at v0, v1; the four rhombus derivatives; Z at the
 // two opposite rhombus vertices; l_e / mean l, d_e / mean d.
 struct FeatIn {
-  const void *vn, *vt, *D, *Z, *DL, *CL, *V;
+  const void *vn, *D, *Z, *DL, *CL, *V;
 };
 template <typename R>
 __device__ __forceinline__ void features(const DevGrid& g, const FeatIn& in, int e, int k, double lbar, double dbar,
@@ -197,8 +274,11 @@ __device__ __forceinline__ void features(const DevGrid& g, const FeatIn& in, int
   const int v0 = g.e2c2v[e], v1 = g.e2c2v[g.es + e], v2 = g.e2c2v[2 * g.es + e], v3 = g.e2c2v[3 * g.es + e];
   const R invd = (R)g.invd[e], invl = (R)g.invl[e], invlr = (R)g.invlr[e];
   const R half = R(0.5);
-  f[0] = (float)static_cast<const R*>(in.vn)[(size_t)k * g.es + e];
-  f[1] = (float)static_cast<const R*>(in.vt)[(size_t)k * g.es + e];
+  const R* vnr = static_cast<const R*>(in.vn) + (size_t)k * g.es;
+  VtStencil<R> vs;
+  vs.load(g, e);
+  f[0] = (float)vnr[e];
+  f[1] = (float)vs.apply(vnr, e);
   f[2] = (float)(half * (dr[c0] + dr[c1]));
   f[3] = (float)((dr[c1] - dr[c0]) * invd);
   f[4] = (float)(half * (zr[v0] + zr[v1]));
@@ -218,41 +298,28 @@ __device__ __forceinline__ void features(const DevGrid& g, const FeatIn& in, int
 }
 
 // ---------------------------------------------------------------------------
-// vt of every edge (input of the features)
+// inference: features -> normalised BF16 -> MLP -> T (denormalised).  Every
+// wave works alone on tiles of 64 consecutive edges of one level, taken in
+// level-major order with a stride of the grid's wave count.  A column with any
+// feature outside the training range gets flag_range[e] = 1 (plain stores
+// of one value: order independent).
 // ---------------------------------------------------------------------------
+constexpr int kInferWaves = 4;
+constexpr int kInferBlocks = 2048;  // persistent: each wave loads the weights once
 template <typename R>
-__global__ void __launch_bounds__(256) k_vt(DevGrid g, const R* __restrict__ vn, R* __restrict__ vt) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (e >= g.ne) return;
-  VtStencil<R> st;
-  st.load(g, e);
-  vt[(size_t)k * g.es + e] = st.apply(vn + (size_t)k * g.es, e);
-}
-
-// ---------------------------------------------------------------------------
-// inference: features -> normalised BF16 -> MLP -> T (denormalised).
-// Block = 2 waves = 128 consecutive edges of one level; the grid loops over
-// (level, edge tile).  A column with any feature outside the training range
-// gets flag_range[e] = 1 (plain stores of one value: order independent).
-// ---------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(128) k_infer(DevGrid g, FeatIn fin, const float* __restrict__ par, const Norm* __restrict__ nrm,
-                                               double lbar, double dbar, R* __restrict__ tout,
-                                               int* __restrict__ flag_range) {
-  __shared__ SW s;
-  __shared__ alignas(16) bf16 xs_all[2][64 * XS];
-  __shared__ alignas(16) bf16 hs_all[2][16 * HS];
-  stage_weights(s, par, nullptr);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, q = l >> 4;
+__global__ void __launch_bounds__(64 * kInferWaves) k_infer(DevGrid g, FeatIn fin, const float* __restrict__ par,
+                                                            const Norm* __restrict__ nrm, double lbar, double dbar,
+                                                            R* __restrict__ tout, int* __restrict__ flag_range) {
+  __shared__ alignas(16) bf16 xs_all[kInferWaves][64 * XS];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   bf16* xs = xs_all[w];
-  bf16* hs = hs_all[w];
-  const int ntx = (g.ne + 127) / 128;
+  RegNet n;
+  load_net(n, par);
+  const int ntx = (g.ne + 63) / 64;
   const int total = ntx * g.K;
-  __syncthreads();
-  for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
-    const int k = tile / ntx, e0 = (tile % ntx) * 128 + w * 64;
-    const int e = e0 + l;
+  const int nwave = gridDim.x * kInferWaves;
+  for (int tile = blockIdx.x * kInferWaves + w; tile < total; tile += nwave) {
+    const int k = tile / ntx, e = (tile % ntx) * 64 + l;
     float f[NIN];
     if (e < g.ne) {
       features<R>(g, fin, e, k, lbar, dbar, f);
@@ -260,23 +327,16 @@ __global__ void __launch_bounds__(128) k_infer(DevGrid g, FeatIn fin, const floa
 #pragma unroll
       for (int i = 0; i < NIN; ++i) out |= !(f[i] >= nrm->fmin[i] && f[i] <= nrm->fmax[i]);
       if (out) flag_range[e] = 1;
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) f[i] = (f[i] - nrm->mean[i]) * nrm->istd[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < NIN; ++i) f[i] = nrm->mean[i];
+      for (int i = 0; i < NIN; ++i) f[i] = 0.0f;
     }
-#pragma unroll
-    for (int i = 0; i < XK; ++i) xs[l * XS + i] = i < NIN ? to_bf16((f[i] - nrm->mean[i]) * nrm->istd[i]) : (bf16)0;
+    put_row(xs, f);
     wave_lds_sync();
-    float y[4][4];
-    forward64(s, xs, hs, y);
-#pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (j == t) {
-          const int ee = e0 + 16 * st + 4 * q + t;
-          if (ee < g.ne) tout[(size_t)k * g.es + ee] = (R)(y[st][t] * nrm->tstd);
-        }
+    const float y = forward_t(n, xs);
+    if (e < g.ne) tout[(size_t)k * g.es + e] = (R)(y * nrm->tstd);
     wave_lds_sync();
   }
 }
@@ -668,35 +728,25 @@ __global__ void __launch_bounds__(256) k_adam(const float* __restrict__ part, in
   }
 }
 
-// forward of raw feature rows [n][18] (tests and evaluation): y = T
-__global__ void __launch_bounds__(128) k_forward_rows(const float* __restrict__ par, const Norm* __restrict__ nrm,
-                                                      const float* __restrict__ x, long long n,
-                                                      float* __restrict__ y) {
-  __shared__ SW s;
-  __shared__ alignas(16) bf16 xs_all[2][64 * XS];
-  __shared__ alignas(16) bf16 hs_all[2][16 * HS];
-  stage_weights(s, par, nullptr);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, q = l >> 4;
+// forward of raw feature rows [n][18] (tests and evaluation): y = T, by the
+// inference path (one wave per 64 rows)
+__global__ void __launch_bounds__(64 * kInferWaves) k_forward_rows(const float* __restrict__ par,
+                                                                   const Norm* __restrict__ nrm,
+                                                                   const float* __restrict__ x, long long n,
+                                                                   float* __restrict__ y) {
+  __shared__ alignas(16) bf16 xs_all[kInferWaves][64 * XS];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   bf16* xs = xs_all[w];
-  const long long r0 = blockIdx.x * 128ll + w * 64;
-  const long long r = r0 + l;
+  RegNet net;
+  load_net(net, par);
+  const long long r = (blockIdx.x * (long long)kInferWaves + w) * 64 + l;
+  float v[NIN];
 #pragma unroll
-  for (int i = 0; i < XK; ++i) {
-    float v = 0.f;
-    if (i < NIN && r < n) v = (x[r * NIN + i] - nrm->mean[i]) * nrm->istd[i];
-    xs[l * XS + i] = to_bf16(v);
-  }
-  __syncthreads();
-  float yy[4][4];
-  forward64(s, xs, hs_all[w], yy);
-#pragma unroll
-  for (int st = 0; st < 4; ++st)
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (j == t) {
-        const long long rr = r0 + 16 * st + 4 * q + t;
-        if (rr < n) y[rr] = yy[st][t] * nrm->tstd;
-      }
+  for (int i = 0; i < NIN; ++i) v[i] = r < n ? (x[r * NIN + i] - nrm->mean[i]) * nrm->istd[i] : 0.0f;
+  put_row(xs, v);
+  wave_lds_sync();
+  const float yy = forward_t(net, xs);
+  if (r < n) y[r] = yy * nrm->tstd;
 }
 
 }  // namespace
@@ -755,8 +805,7 @@ void mean_lengths(const HostGrid& h, double* lbar, double* dbar) {
 
 // The plain diffusion's front on the current vn (w diffused into the state's
 // w with the fresh viscosity; curl L1 into its own buffer so that the
-// vorticity survives), then vt for the features into the substep workspace
-// field vns (idle during the diffusion).
+// vorticity survives); the features read its fields.
 template <typename R>
 FeatIn front_and_features(dc_state* s, const StepCoef& c, hipStream_t st) {
   const DevGrid& g = s->d;
@@ -766,8 +815,7 @@ FeatIn front_and_features(dc_state* s, const StepCoef& c, hipStream_t st) {
                             static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
                             static_cast<R*>(s->zeta), static_cast<R*>(s->sur_cl), static_cast<R*>(s->vv), c, s->tiles,
                             st, nullptr);
-  k_vt<R><<<dim3((g.ne + 255) / 256, g.K), 256, 0, st>>>(g, vn, static_cast<R*>(s->vns));
-  return FeatIn{vn, s->vns, s->kc, s->zeta, s->d2, s->sur_cl, s->vv};
+  return FeatIn{vn, s->kc, s->zeta, s->d2, s->sur_cl, s->vv};
 }
 
 }  // namespace
@@ -792,16 +840,17 @@ void surrogate_diffusion(dc_state* s, const StepCoef& c) {
   ++sc.steps;
   const FeatIn fin = front_and_features<R>(s, c, st);
   k_fill_int<<<(g.ne + 255) / 256, 256, 0, st>>>(s->sur_fr, g.ne, 0);
-  const int total = ((g.ne + 127) / 128) * g.K;
-  k_infer<R><<<std::min(total, 4096), 128, 0, st>>>(g, fin, sc.mlp->par, sc.mlp->nrm, s->sur_lbar, s->sur_dbar, tm,
-                                                    s->sur_fr);
+  const int tiles = ((g.ne + 63) / 64) * g.K;
+  const int blocks = std::min((tiles + kInferWaves - 1) / kInferWaves, kInferBlocks);
+  k_infer<R><<<blocks, 64 * kInferWaves, 0, st>>>(g, fin, sc.mlp->par, sc.mlp->nrm, s->sur_lbar, s->sur_dbar, tm,
+                                                  s->sur_fr);
   const R* l1 = static_cast<const R*>(s->vt);
   const R* nu = static_cast<const R*>(s->tvn0);
   const R* dl1 = static_cast<const R*>(s->d2);
   const R* cl1 = static_cast<const R*>(s->sur_cl);
   if (judge) {
     ++sc.judge_steps;
-    R* old = static_cast<R*>(s->vns);  // vt is no longer needed
+    R* old = static_cast<R*>(s->vns);  // substep workspace, idle during the diffusion
     k_copy<R><<<1024, 256, 0, st>>>(vn, old, (size_t)g.K * g.es);
     launch_diffusion_back<R>(g, vn, l1, nu, dl1, cl1, c, s->tiles, st, nullptr);
     k_fill_int<<<1, 64, 0, st>>>(s->sur_cnt, 1, 0);
@@ -1063,7 +1112,7 @@ dc_status dc_mlp_forward(dc_mlp* M, const float* host_x, int64_t n, float* host_
   hipError_t e = hipMalloc(&y, (size_t)n * 4);
   if (e == hipSuccess) e = hipMemcpy(x, host_x, (size_t)n * NIN * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
-    k_forward_rows<<<(unsigned)((n + 127) / 128), 128>>>(M->par, M->nrm, x, n, y);
+    k_forward_rows<<<(unsigned)((n + 64 * kInferWaves - 1) / (64 * kInferWaves)), 64 * kInferWaves>>>(M->par, M->nrm, x, n, y);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpy(host_y, y, (size_t)n * 4, hipMemcpyDeviceToHost);
