@@ -68,7 +68,7 @@ Layout workspace_layout(const HostGrid& h, dc_precision prec, dc_diffusion diff,
   L.kc = take(K * std::max(h.es, h.cs) * r);  // K_e [K][es] in substeps, div vn [K][cs] in diffusion
   L.d2 = take(K1 * h.cs * r);
   L.zeta = take(K * h.vs * r);
-  L.vv = take(3 * K * h.vs * r);
+  L.vv = take(4 * K * h.vs * r);  // vertex vector and vorticity (bodies::VertexQ)
   L.gw = take(K1 * h.es * r);
   L.dvn = take(K * h.cs * r);
   L.wstar = take(K1 * h.cs * 8);

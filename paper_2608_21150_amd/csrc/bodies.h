@@ -1195,6 +1195,38 @@ struct BCol {
 //
 // first vector Laplacian at edge e, grad(div vn) - gradt(curl vn), and the
 // Smagorinsky viscosity from the rhombus deformation of the vertex vectors
+// Vertex quantities of the diffusion's first pass: the least-squares vertex
+// vector (x, y, z) and the relative vorticity.  FP32 keeps them interleaved
+// per vertex, one 16-byte record that one load brings in (diff_edge1 -46 %
+// on R2B8); FP64 keeps four planes [4][K][vs] (x, y, z, vorticity), since
+// its 32-byte records need two half-record accesses per vertex and measured
+// slower than the planes.  Index i = level * vs + vertex; plane = K * vs.
+template <typename R>
+struct alignas(4 * sizeof(R)) VVec {
+  R x, y, z, zeta;
+};
+template <typename R>
+struct VertexQ {
+  static constexpr bool kInterleaved = sizeof(R) == 4;
+  __device__ __forceinline__ static VVec<R> load(const R* __restrict__ base, size_t plane, size_t i) {
+    if constexpr (kInterleaved) {
+      return reinterpret_cast<const VVec<R>*>(base)[i];
+    } else {
+      return VVec<R>{base[i], base[plane + i], base[2 * plane + i], base[3 * plane + i]};
+    }
+  }
+  __device__ __forceinline__ static void store(R* __restrict__ base, size_t plane, size_t i, const VVec<R>& v) {
+    if constexpr (kInterleaved) {
+      reinterpret_cast<VVec<R>*>(base)[i] = v;
+    } else {
+      base[i] = v.x;
+      base[plane + i] = v.y;
+      base[2 * plane + i] = v.z;
+      base[3 * plane + i] = v.zeta;
+    }
+  }
+};
+
 template <typename R>
 struct Edge1Geo {
   int c0, c1, rv[4];
@@ -1219,34 +1251,33 @@ struct Edge1Geo {
     smag = (R)(cf.cs * ae);
     cap = (R)(ae / (cf.cap * cf.dt));
   }
-  __device__ __forceinline__ R l1(const R* dr, const R* zr) const {
-    return (dr[c1] - dr[c0]) * invd - (zr[rv[1]] - zr[rv[0]]) * invl;
+  // the rhombus vertices' quantities at level k
+  __device__ __forceinline__ void gather(const DevGrid& g, const R* vv, int k, VVec<R> q[4]) const {
+    const size_t plane = (size_t)g.K * g.vs, row = (size_t)k * g.vs;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = VertexQ<R>::load(vv, plane, row + rv[i]);
+  }
+  __device__ __forceinline__ R l1(const R* dr, const VVec<R> q[4]) const {
+    return (dr[c1] - dr[c0]) * invd - (q[1].zeta - q[0].zeta) * invl;
   }
   // derivatives of the normal and tangential wind across the rhombus from the
-  // vertex vectors (vx, vy, vz: the three components at one level):
-  // d = {dvn/dt, dvt/dt, dvn/dn, dvt/dn}
-  __device__ __forceinline__ void rhombus(const R* vx, const R* vy, const R* vz, R d[4]) const {
-    const R tx = vx[rv[1]] - vx[rv[0]], ty = vy[rv[1]] - vy[rv[0]], tz = vz[rv[1]] - vz[rv[0]];
-    const R nx = vx[rv[3]] - vx[rv[2]], ny = vy[rv[3]] - vy[rv[2]], nz = vz[rv[3]] - vz[rv[2]];
+  // vertex vectors: d = {dvn/dt, dvt/dt, dvn/dn, dvt/dn}
+  __device__ __forceinline__ void rhombus(const VVec<R> q[4], R d[4]) const {
+    const R tx = q[1].x - q[0].x, ty = q[1].y - q[0].y, tz = q[1].z - q[0].z;
+    const R nx = q[3].x - q[2].x, ny = q[3].y - q[2].y, nz = q[3].z - q[2].z;
     d[0] = (tx * n[0] + ty * n[1] + tz * n[2]) * invl;
     d[1] = (tx * t[0] + ty * t[1] + tz * t[2]) * invl;
     d[2] = (nx * n[0] + ny * n[1] + nz * n[2]) * invlr;
     d[3] = (nx * t[0] + ny * t[1] + nz * t[2]) * invlr;
   }
-  __device__ __forceinline__ R nu(const R* vx, const R* vy, const R* vz) const {
+  __device__ __forceinline__ R nu(const VVec<R> q[4]) const {
     R d[4];
-    rhombus(vx, vy, vz, d);
+    rhombus(q, d);
     const R a = d[2] - d[1], b = d[3] + d[0];
     const R def = sqrt(a * a + b * b);
     return fmin(smag * def, cap);
   }
 };
-template <typename R>
-__device__ __forceinline__ void dif_rhombus(const DevGrid& g, const R* vx, const R* vy, const R* vz, int e, R d[4]) {
-  Edge1Geo<R> q;
-  q.load_rhombus(g, e);
-  q.rhombus(vx, vy, vz, d);
-}
 // divergence at cell c of an edge field row
 template <typename R>
 struct DivGeo {
@@ -1329,14 +1360,12 @@ struct BDvert {
   struct Args {
     const R* vn;
     R* vv;
-    R* zeta;
     int kb;
   };
   static constexpr int kThreads = 256;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const R* __restrict__ vn = args.vn;
     R* __restrict__ vv = args.vv;
-    R* __restrict__ zeta = args.zeta;
     const int kb = args.kb;
     const int v = bx * blockDim.x + threadIdx.x;
     if (v >= g.nv) return;
@@ -1349,7 +1378,6 @@ struct BDvert {
   #pragma unroll
       for (int j = 0; j < 3; ++j) lw[j][s] = (R)g.klsq[(j * 6 + s) * g.vs + v];
     }
-    const size_t plane = (size_t)g.K * g.vs;
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
     for (int k = k0; k < k1; ++k) {
       const R* row = vn + (size_t)k * g.es;
@@ -1364,11 +1392,7 @@ struct BDvert {
         b += lw[1][s] * x[s];
         d += lw[2][s] * x[s];
       }
-      const size_t o = (size_t)k * g.vs + v;
-      zeta[o] = z;
-      vv[o] = a;
-      vv[plane + o] = b;
-      vv[2 * plane + o] = d;
+      VertexQ<R>::store(vv, (size_t)g.K * g.vs, (size_t)k * g.vs + v, VVec<R>{a, b, d, z});
     }
   }
 };
@@ -1411,7 +1435,6 @@ struct BDedge1 {
   using Real = R;
   struct Args {
     const R* dv;
-    const R* zeta;
     const R* vv;
     R* l1;
     R* nu;
@@ -1421,7 +1444,6 @@ struct BDedge1 {
   static constexpr int kThreads = 256;
   __device__ static void run(const DevGrid& g, const Args& args, int bx, int by) {
     const R* __restrict__ dv = args.dv;
-    const R* __restrict__ zeta = args.zeta;
     const R* __restrict__ vv = args.vv;
     R* __restrict__ l1 = args.l1;
     R* __restrict__ nu = args.nu;
@@ -1429,16 +1451,14 @@ struct BDedge1 {
     const int kb = args.kb;
     const int e = bx * blockDim.x + threadIdx.x;
     if (e >= g.ne) return;
-    const size_t plane = (size_t)g.K * g.vs;
     Edge1Geo<R> q;
     q.load(g, e, cf);
     const int k0 = by * kb, k1 = min(g.K, k0 + kb);
     for (int k = k0; k < k1; ++k) {
-      const R* dr = dv + (size_t)k * g.cs;
-      const R* zr = zeta + (size_t)k * g.vs;
-      l1[(size_t)k * g.es + e] = q.l1(dr, zr);
-      const R* vx = vv + (size_t)k * g.vs;
-      nu[(size_t)k * g.es + e] = q.nu(vx, vx + plane, vx + 2 * plane);
+      VVec<R> qv[4];
+      q.gather(g, vv, k, qv);
+      l1[(size_t)k * g.es + e] = q.l1(dv + (size_t)k * g.cs, qv);
+      nu[(size_t)k * g.es + e] = q.nu(qv);
     }
   }
 };
@@ -1744,15 +1764,16 @@ struct DiffusionArgs {
 };
 
 // vn updated in place; w read from w_in, written to w_out; l1, nu, dv, dl1,
-// zeta, vv are workspace fields (edge, edge, cell, cell, vertex, 3 x vertex)
+// zeta (curl L1), vv are workspace fields (edge, edge, cell, cell, vertex,
+// 4 x vertex: vertex vector and vorticity of vn, laid out as VertexQ says)
 template <typename R>
 DiffusionArgs<R> diffusion_args(const DevGrid& g, R* vn, const double* w_in, double* w_out, R* l1, R* nu, R* dv,
                                 R* dl1, R* zeta, R* vv, const StepCoef& c, const Tile* T,
                                 const ThetaDiff& td = ThetaDiff{nullptr, nullptr, nullptr}) {
   DiffusionArgs<R> d;
-  d.dv = {vn, vv, zeta, T[T_DVERT].kb};
+  d.dv = {vn, vv, T[T_DVERT].kb};
   d.dd = {vn, dv, T[T_DCELL].kb};
-  d.d1 = {dv, zeta, vv, l1, nu, c, T[T_DEDGE].kb};
+  d.d1 = {dv, vv, l1, nu, c, T[T_DEDGE].kb};
   d.cv = {l1, nu, w_in, w_out, dl1, zeta, td.th_in, td.th_out, td.ex, cdiv(g.nc, T[T_DCELL].threads), c,
           T[T_DCELL].kb};
   d.d2 = {vn, l1, nu, dl1, zeta, c, T[T_DEDGE].kb};

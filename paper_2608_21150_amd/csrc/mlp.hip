@@ -249,30 +249,31 @@ __device__ __forceinline__ void put_row(bf16* xs, const float* v) {
 }
 
 // The 18 raw features of edge e at level k, from vn (edges; vt formed here
-// with the step's tangential-wind stencil), D = div vn
-// (cells), Z = curl vn (vertices), DL = div L1 (cells), CL = curl L1
-// (vertices) and the vertex vectors V (three component planes `plane`
-// apart); the fields are those of the plain diffusion.  Stencil values
-// enter as centred pairs, the mean of the two points and their difference
-// over their distance, formed in the path's precision before the network's
-// BF16 rounding: vn_e, vt_e; D at c0, c1; Z at the end vertices v0, v1;
-// div L1 at c0, c1; curl L1 at v0, v1; the four rhombus derivatives; Z at the
-// two opposite rhombus vertices; l_e / mean l, d_e / mean d.
+// with the step's tangential-wind stencil), D = div vn (cells), DL = div L1
+// (cells), CL = curl L1 (vertices) and the vertex quantities V (vertex
+// vector and Z = curl vn, laid out as VertexQ says); the fields are those of
+// the plain diffusion.  Stencil values enter as centred pairs, the mean of
+// the two points and their difference over their distance, formed in the
+// path's precision before the network's BF16 rounding: vn_e, vt_e; D at c0,
+// c1; Z at the end vertices v0, v1; div L1 at c0, c1; curl L1 at v0, v1; the
+// four rhombus derivatives; Z at the two opposite rhombus vertices;
+// l_e / mean l, d_e / mean d.
 struct FeatIn {
-  const void *vn, *D, *Z, *DL, *CL, *V;
+  const void *vn, *D, *DL, *CL, *V;
 };
 template <typename R>
 __device__ __forceinline__ void features(const DevGrid& g, const FeatIn& in, int e, int k, double lbar, double dbar,
                                          float f[NIN]) {
-  const size_t plane = (size_t)g.K * g.vs;
   const R* dr = static_cast<const R*>(in.D) + (size_t)k * g.cs;
-  const R* zr = static_cast<const R*>(in.Z) + (size_t)k * g.vs;
   const R* dlr = static_cast<const R*>(in.DL) + (size_t)k * g.cs;
   const R* clr = static_cast<const R*>(in.CL) + (size_t)k * g.vs;
-  const R* vx = static_cast<const R*>(in.V) + (size_t)k * g.vs;
+  Edge1Geo<R> q;
+  q.load_rhombus(g, e);
+  VVec<R> qv[4];
+  q.gather(g, static_cast<const R*>(in.V), k, qv);
   const int c0 = g.e2c[e], c1 = g.e2c[g.es + e];
-  const int v0 = g.e2c2v[e], v1 = g.e2c2v[g.es + e], v2 = g.e2c2v[2 * g.es + e], v3 = g.e2c2v[3 * g.es + e];
-  const R invd = (R)g.invd[e], invl = (R)g.invl[e], invlr = (R)g.invlr[e];
+  const int v0 = q.rv[0], v1 = q.rv[1];
+  const R invd = (R)g.invd[e], invl = q.invl, invlr = q.invlr;
   const R half = R(0.5);
   const R* vnr = static_cast<const R*>(in.vn) + (size_t)k * g.es;
   VtStencil<R> vs;
@@ -281,18 +282,18 @@ __device__ __forceinline__ void features(const DevGrid& g, const FeatIn& in, int
   f[1] = (float)vs.apply(vnr, e);
   f[2] = (float)(half * (dr[c0] + dr[c1]));
   f[3] = (float)((dr[c1] - dr[c0]) * invd);
-  f[4] = (float)(half * (zr[v0] + zr[v1]));
-  f[5] = (float)((zr[v1] - zr[v0]) * invl);
+  f[4] = (float)(half * (qv[0].zeta + qv[1].zeta));
+  f[5] = (float)((qv[1].zeta - qv[0].zeta) * invl);
   f[6] = (float)(half * (dlr[c0] + dlr[c1]));
   f[7] = (float)((dlr[c1] - dlr[c0]) * invd);
   f[8] = (float)(half * (clr[v0] + clr[v1]));
   f[9] = (float)((clr[v1] - clr[v0]) * invl);
   R d[4];
-  dif_rhombus<R>(g, vx, vx + plane, vx + 2 * plane, e, d);
+  q.rhombus(qv, d);
 #pragma unroll
   for (int i = 0; i < 4; ++i) f[10 + i] = (float)d[i];
-  f[14] = (float)(half * (zr[v2] + zr[v3]));
-  f[15] = (float)((zr[v3] - zr[v2]) * invlr);
+  f[14] = (float)(half * (qv[2].zeta + qv[3].zeta));
+  f[15] = (float)((qv[3].zeta - qv[2].zeta) * invlr);
   f[16] = (float)(1.0 / (g.invl[e] * lbar));
   f[17] = (float)(1.0 / (g.invd[e] * dbar));
 }
@@ -815,7 +816,7 @@ FeatIn front_and_features(dc_state* s, const StepCoef& c, hipStream_t st) {
                             static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
                             static_cast<R*>(s->zeta), static_cast<R*>(s->sur_cl), static_cast<R*>(s->vv), c, s->tiles,
                             st, nullptr);
-  return FeatIn{vn, s->kc, s->zeta, s->d2, s->sur_cl, s->vv};
+  return FeatIn{vn, s->kc, s->d2, s->sur_cl, s->vv};
 }
 
 }  // namespace
