@@ -226,6 +226,47 @@ dc_status dc_state_write(dc_state *st, int32_t field, const double *host, size_t
  * then diffusion with dt.  Asynchronous on the state's stream.
  * DC_EINVAL: dt <= 0 or not finite, nsubsteps < 1. */
 dc_status dc_dycore_step(dc_state *st, double dt, int32_t nsubsteps);
+/* The step in parts, for verification of the segments that lie between
+ * halo exchanges one at a time against a reference given the same input
+ * fields (paper, Section 4.4, first level of the verification hierarchy).
+ * dc_dycore_part runs one part with the coefficients of a step (dt,
+ * nsubsteps), asynchronously on the state's stream:
+ *   DC_PART_PREDICTOR  the predictor of one substep of dt/nsubsteps from
+ *                      the current buffer set (advective tendencies at the
+ *                      substep start, the momentum update to vn*, the
+ *                      vertically implicit solve for w*).  Writes workspace
+ *                      fields only; the buffer set and its contents are
+ *                      unchanged.
+ *   DC_PART_CORRECTOR  the corrector of that substep: reads the current
+ *                      buffer set and what the last DC_PART_PREDICTOR left
+ *                      in the workspace, writes the other buffer set and
+ *                      makes it current.  PREDICTOR then CORRECTOR equals
+ *                      one substep bit for bit.
+ *   DC_PART_DIFFUSION  the plain diffusion of one step of dt on the current
+ *                      buffer set, in place (w, and theta_v with the theta_v
+ *                      diffusion option, are first copied to the staging
+ *                      fields that the last substep of a step fills).
+ * DC_EINVAL: bad part, dt <= 0 or not finite, nsubsteps outside [1, 1000].
+ * DC_ESTATE: DC_PART_DIFFUSION on a state created without the plain
+ * diffusion, DC_PART_CORRECTOR before any DC_PART_PREDICTOR (or after a
+ * step or another corrector). */
+enum { DC_PART_PREDICTOR = 0, DC_PART_CORRECTOR = 1, DC_PART_DIFFUSION = 2 };
+dc_status dc_dycore_part(dc_state *st, int32_t part, double dt, int32_t nsubsteps);
+/* Synchronising host copy, in FP64 (unpadded [level][entity], original
+ * numbering, like dc_state_read), of a workspace field that the last
+ * DC_PART_PREDICTOR wrote:
+ *   DC_WORK_VN_PRED  vn* = vn + dtau (T_vn - cpd theta_e grad pi')   [K][E]
+ *   DC_WORK_Y        vn + dtau (a0 T_vn - cpd theta_e grad pi'), the
+ *                    part of the corrector's vn that the predictor forms [K][E]
+ *   DC_WORK_W_PRED   w* from the implicit solve                      [K+1][C]
+ *   DC_WORK_T_W      T_w at the substep start on the half levels
+ *                    1..K-1 (rows 0 and K are returned as 0)         [K+1][C]
+ *   DC_WORK_DIV      div vn* (input of the corrector's damping)      [K][C]
+ * Mixed precision: vn*, Y, T_w and div vn* are stored in FP32.  n must equal
+ * the element count.  DC_ESTATE if no DC_PART_PREDICTOR ran since the state
+ * was created or last stepped. */
+enum { DC_WORK_VN_PRED = 0, DC_WORK_Y, DC_WORK_W_PRED, DC_WORK_T_W, DC_WORK_DIV, DC_WORK_COUNT };
+dc_status dc_state_read_work(dc_state *st, int32_t which, double *host, size_t n);
 /* Synchronising conservation diagnostics of the current buffer (fixed
  * reduction order: reproducible run to run). */
 dc_status dc_diag_conservation(dc_state *st, dc_diag *out);

@@ -255,6 +255,35 @@ void enqueue_trial_step(dc_state* s, double dt, int nsub) {
   }
 }
 
+// One part of a step (dc_dycore_part): the predictor or the corrector of one
+// substep on the current buffer set, or the plain diffusion with its inputs
+// first staged where the last substep of a step would have put them.
+template <typename R>
+hipError_t enqueue_part(dc_state* s, int part, double dt, int nsub) {
+  const StepCoef c = make_coef(s, dt, nsub);
+  if (part == DC_PART_PREDICTOR) {
+    launch_predictor<R>(s->d, substep_bufs<R>(s, s->cur, false), c, s->tiles, s->stream, &s->prof);
+    s->part = 1;
+  } else if (part == DC_PART_CORRECTOR) {
+    launch_corrector<R>(s->d, substep_bufs<R>(s, s->cur, false), c, s->tiles, s->stream, &s->prof);
+    s->cur ^= 1;
+    s->part = 2;
+  } else {
+    const dc_fields& cur = s->buf[s->cur];
+    const size_t K = s->grid->h.K, cs = s->grid->h.cs;
+    s->part = 0;
+    hipError_t e = hipMemcpyAsync(s->wtmp, cur.w, (K + 1) * cs * 8, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && s->p.diffuse_theta)
+      e = hipMemcpyAsync(s->ttmp, cur.theta_v, K * cs * 8, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return e;
+    launch_diffusion<R>(s->d, static_cast<R*>(cur.vn), s->wtmp, static_cast<double*>(cur.w), static_cast<R*>(s->vt),
+                        static_cast<R*>(s->tvn0), static_cast<R*>(s->kc), static_cast<R*>(s->d2),
+                        static_cast<R*>(s->zeta), static_cast<R*>(s->vv), theta_diff(s, cur), c, s->tiles, s->stream,
+                        &s->prof);
+  }
+  return hipSuccess;
+}
+
 dc_status run_diag(dc_state* s, dc_diag* out) {
   const dc_fields& f = s->buf[s->cur];
   if (s->prec == DC_PREC_MIXED)
@@ -588,6 +617,7 @@ dc_status dc_dycore_step(dc_state* s, double dt, int32_t nsub) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DC_EINVAL, "dt must be finite and > 0");
   if (nsub < 1 || nsub > 1000) return fail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
   if (s->diff == DC_DIFF_SURROGATE && !s->sur) return fail(DC_ESTATE, "surrogate mode needs dc_state_set_mlp first");
+  s->part = 0;
   if (s->prec == DC_PREC_MIXED)
     enqueue_step<float>(s, dt, nsub);
   else
@@ -598,6 +628,55 @@ dc_status dc_dycore_step(dc_state* s, double dt, int32_t nsub) {
     dc_status st = run_diag(s, &d);
     if (st != DC_OK) return st;
     if (d.n_nonfinite > 0) return fail(DC_ENONFINITE, "state holds non-finite values");
+  }
+  return DC_OK;
+}
+
+dc_status dc_dycore_part(dc_state* s, int32_t part, double dt, int32_t nsub) {
+  if (!s) return fail(DC_EINVAL, "state is NULL");
+  if (part < DC_PART_PREDICTOR || part > DC_PART_DIFFUSION) return fail(DC_EINVAL, "bad part");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DC_EINVAL, "dt must be finite and > 0");
+  if (nsub < 1 || nsub > 1000) return fail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
+  if (part == DC_PART_CORRECTOR && s->part != 1) return fail(DC_ESTATE, "the corrector needs a predictor just before");
+  if (part == DC_PART_DIFFUSION && s->diff != DC_DIFF_PLAIN)
+    return fail(DC_ESTATE, "the diffusion part needs a state with the plain diffusion");
+  DC_TRY(s->prec == DC_PREC_MIXED ? enqueue_part<float>(s, part, dt, nsub) : enqueue_part<double>(s, part, dt, nsub));
+  DC_TRY(hipGetLastError());
+  return DC_OK;
+}
+
+dc_status dc_state_read_work(dc_state* s, int32_t which, double* host, size_t n) {
+  if (!s || !host) return fail(DC_EINVAL, "NULL argument");
+  if (which < 0 || which >= DC_WORK_COUNT) return fail(DC_EINVAL, "bad workspace field id");
+  if (s->part == 0) return fail(DC_ESTATE, "no predictor part ran since the workspace was last overwritten");
+  const HostGrid& h = s->grid->h;
+  const bool edge = which == DC_WORK_VN_PRED || which == DC_WORK_Y;
+  const bool half = which == DC_WORK_W_PRED || which == DC_WORK_T_W;
+  const int levels = half ? h.K + 1 : h.K;
+  const int nent = edge ? h.ne : h.nc, stride = edge ? h.es : h.cs;
+  if (n != (size_t)levels * nent) return fail(DC_EINVAL, "host array size mismatch");
+  const bool f32 = which != DC_WORK_W_PRED && s->prec == DC_PREC_MIXED;
+  const void* src = which == DC_WORK_VN_PRED ? s->vns
+                    : which == DC_WORK_Y     ? s->tvn0
+                    : which == DC_WORK_W_PRED ? static_cast<const void*>(s->wstar)
+                    : which == DC_WORK_T_W   ? s->tw0
+                                             : s->dvn;
+  const size_t np = (size_t)levels * stride;
+  std::vector<double> tmp(f32 ? 0 : np);
+  std::vector<float> tmpf(f32 ? np : 0);
+  DC_TRY(hipStreamSynchronize(s->stream));
+  if (f32)
+    DC_TRY(hipMemcpy(tmpf.data(), src, np * 4, hipMemcpyDeviceToHost));
+  else
+    DC_TRY(hipMemcpy(tmp.data(), src, np * 8, hipMemcpyDeviceToHost));
+  const std::vector<int32_t>& perm = edge ? h.perm_e : h.perm_c;
+  for (int k = 0; k < levels; ++k) {
+    // T_w lives on the interior half levels only
+    const bool zero = which == DC_WORK_T_W && (k == 0 || k == h.K);
+    for (int i = 0; i < nent; ++i) {
+      const size_t si = (size_t)k * stride + i;
+      host[(size_t)k * nent + perm[i]] = zero ? 0.0 : (f32 ? (double)tmpf[si] : tmp[si]);
+    }
   }
   return DC_OK;
 }
@@ -627,6 +706,7 @@ dc_status dc_state_autotune(dc_state* s, double dt, int32_t nsub) {
   if (!s) return fail(DC_EINVAL, "state is NULL");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DC_EINVAL, "dt must be finite and > 0");
   if (nsub < 1 || nsub > 1000) return fail(DC_EINVAL, "nsubsteps must be in [1, 1000]");
+  s->part = 0;  // the trial steps overwrite the workspace
   DC_TRY(hipStreamSynchronize(s->stream));
   // the trial steps advance the state: keep a copy of the current fields
   const int parity = s->cur;

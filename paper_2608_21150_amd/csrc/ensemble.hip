@@ -325,6 +325,7 @@ dc_status step_impl(dc_ensemble* E, double dt, int nsub, StepMode mode, Prof* pr
 }
 
 dc_status ens_step(dc_ensemble* E, double dt, int nsub, StepMode mode, Prof* prof) {
+  for (dc_state* s : E->m) s->part = 0;  // the members' workspaces are overwritten
   if (E->prec == DC_PREC_MIXED) return step_impl<float>(E, dt, nsub, mode, prof);
   return step_impl<double>(E, dt, nsub, mode, prof);
 }

@@ -114,6 +114,15 @@ struct Bufs {
 template <typename R>
 void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* tiles, hipStream_t s,
                     Prof* prof);
+// the two halves of a substep: the predictor writes only workspace fields
+// (vn*, Y, w*, T_w at the start, div vn*, the edge terms of T_w); the
+// corrector reads them and writes the next buffer set
+template <typename R>
+void launch_predictor(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* tiles, hipStream_t s,
+                      Prof* prof);
+template <typename R>
+void launch_corrector(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* tiles, hipStream_t s,
+                      Prof* prof);
 // theta_v diffusion (optional): theta_v read from th_in, written to th_out,
 // exner updated in place; all null when it is off
 struct ThetaDiff {

@@ -160,18 +160,32 @@ void one_col(int id, const DevGrid& g, const bodies::ColPhaseArgs<R>& a, const T
 }  // namespace
 
 template <typename R>
-void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* T, hipStream_t s, Prof* prof) {
+void launch_predictor(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* T, hipStream_t s,
+                      Prof* prof) {
   using namespace bodies;
   const SubstepArgs<R> a = substep_args<R>(g, b, c, T);
-  // predictor: advective tendencies at the substep start, momentum, column
+  // advective tendencies at the substep start, momentum, column
   one<BVc<R, false>>(K_VC_P, g, a.vc_p, T, s, prof);
   if (c.miura) one<BMiura<R>>(K_MIURA, g, a.mi, T, s, prof);  // needs vt of the start vn
   one<BEdge<R, false>>(K_EDGE_P, g, a.e_p, T, s, prof);
   one_col<R, false>(K_COL_P, g, a.c_p, T, s, prof);
-  // corrector: tendencies at the predicted state, damping, momentum, column
+}
+
+template <typename R>
+void launch_corrector(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* T, hipStream_t s,
+                      Prof* prof) {
+  using namespace bodies;
+  const SubstepArgs<R> a = substep_args<R>(g, b, c, T);
+  // tendencies at the predicted state, damping, momentum, column
   one<BVc<R, true>>(K_VC_C, g, a.vc_c, T, s, prof);
   one<BEdge<R, true>>(K_EDGE_C, g, a.e_c, T, s, prof);
   one_col<R, true>(K_COL_C, g, a.c_c, T, s, prof);
+}
+
+template <typename R>
+void launch_substep(const DevGrid& g, const Bufs<R>& b, const StepCoef& c, const Tile* T, hipStream_t s, Prof* prof) {
+  launch_predictor<R>(g, b, c, T, s, prof);
+  launch_corrector<R>(g, b, c, T, s, prof);
 }
 
 template <typename R>
@@ -217,6 +231,14 @@ void launch_diag(const DevGrid& g, const R* vn, const double* w, const double* r
   k_diag_final<<<1, kDiagThreads, 0, s>>>(partial, ncb + neb, out);
 }
 
+template void launch_predictor<double>(const DevGrid&, const Bufs<double>&, const StepCoef&, const Tile*,
+                                       hipStream_t, Prof*);
+template void launch_predictor<float>(const DevGrid&, const Bufs<float>&, const StepCoef&, const Tile*, hipStream_t,
+                                      Prof*);
+template void launch_corrector<double>(const DevGrid&, const Bufs<double>&, const StepCoef&, const Tile*,
+                                       hipStream_t, Prof*);
+template void launch_corrector<float>(const DevGrid&, const Bufs<float>&, const StepCoef&, const Tile*, hipStream_t,
+                                      Prof*);
 template void launch_substep<double>(const DevGrid&, const Bufs<double>&, const StepCoef&, const Tile*, hipStream_t,
                                      Prof*);
 template void launch_substep<float>(const DevGrid&, const Bufs<float>&, const StepCoef&, const Tile*, hipStream_t,

@@ -1199,6 +1199,7 @@ dc_status dc_surrogate_collect(dc_state* s, double dt, int32_t nsub, uint64_t se
   long long* idx = nullptr;
   if (host_index) ML_TRY(hipMalloc(&idx, (size_t)n_samples * sizeof(long long)));
   const unsigned long long key = seed * 0x9e3779b97f4a7c15ull + 0x632be59bd9b4e019ull;
+  s->part = 0;  // the workspace is overwritten
   const dc_status st = s->prec == DC_PREC_MIXED
                            ? collect_impl<float>(s, dt, nsub, key, n_samples, dev_buf, stride, offset, idx)
                            : collect_impl<double>(s, dt, nsub, key, n_samples, dev_buf, stride, offset, idx);

@@ -62,6 +62,10 @@ struct dc_state {
   int* sur_fr = nullptr;
   int* sur_cnt = nullptr;
   double sur_lbar = 1.0, sur_dbar = 1.0;  // mean primal / dual edge length
+  // the step in parts: 1 after a predictor (its workspace fields readable, a
+  // corrector may follow), 2 after that corrector, 0 once anything else has
+  // run over the workspace
+  int part = 0;
 };
 
 

@@ -19,6 +19,9 @@ DC_OK, DC_EINVAL, DC_EGRID, DC_EHIP, DC_ENOMEM, DC_ENONFINITE, DC_EBUSY, DC_ESTA
 PREC = {"fp64": 0, "mixed": 1}
 DIFF = {"plain": 0, "surrogate": 1, "none": 2}
 FIELDS = ("vn", "w", "rho", "exner", "theta_v")
+# parts of a step (dc_dycore_part) and the predictor's workspace fields (dc_state_read_work)
+PARTS = {"predictor": 0, "corrector": 1, "diffusion": 2}
+WORK = {"vn_pred": 0, "y": 1, "w_pred": 2, "t_w": 3, "div": 4}
 # kernel ids of the per-kernel profile, and the five launch-tile families
 KERNELS = ("vort_ke_pred", "edge_pred", "column_pred", "vort_ke_corr", "edge_corr", "column_corr", "diff_vertex",
            "diff_div", "diff_edge1", "diff_cell_vertex2", "diff_edge2", "edge_upwind")
@@ -130,6 +133,8 @@ def _load():
         "dc_state_read": (ctypes.c_int, [_p, ctypes.c_int32, _f64p, ctypes.c_size_t]),
         "dc_state_write": (ctypes.c_int, [_p, ctypes.c_int32, _f64p, ctypes.c_size_t]),
         "dc_dycore_step": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int32]),
+        "dc_dycore_part": (ctypes.c_int, [_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
+        "dc_state_read_work": (ctypes.c_int, [_p, ctypes.c_int32, _f64p, ctypes.c_size_t]),
         "dc_diag_conservation": (ctypes.c_int, [_p, ctypes.POINTER(Diag)]),
         "dc_state_destroy": (ctypes.c_int, [_p]),
         "dc_state_profile": (ctypes.c_int, [_p, ctypes.c_int32]),
@@ -306,6 +311,20 @@ class State:
 
     def step(self, dt: float, nsub: int):
         check(lib.dc_dycore_step(self.handle, float(dt), int(nsub)))
+
+    def part(self, name: str, dt: float, nsub: int):
+        """One part of a step: "predictor", "corrector" or "diffusion"."""
+        check(lib.dc_dycore_part(self.handle, PARTS[name], float(dt), int(nsub)))
+
+    def read_work(self, name: str) -> np.ndarray:
+        """A workspace field of the last predictor part: "vn_pred", "y",
+        "w_pred", "t_w" or "div" (FP64, unpadded, original numbering)."""
+        K = self.grid.info["n_lev"]
+        nc, ne = self.grid.info["n_cells"], self.grid.info["n_edges"]
+        shape = {"vn_pred": (K, ne), "y": (K, ne), "w_pred": (K + 1, nc), "t_w": (K + 1, nc), "div": (K, nc)}[name]
+        a = np.empty(shape, dtype=np.float64)
+        check(lib.dc_state_read_work(self.handle, WORK[name], a.ctypes.data_as(_f64p), a.size))
+        return a
 
     def current(self) -> int:
         w = ctypes.c_int32()
