@@ -68,6 +68,13 @@ def kernel_bytes(C, E, V, K, r):
     }
 
 
+def mixed_bound(workload, field):
+    """The relative L2 error of the mixed form against FP64 stated per field:
+    1e-4, except w on the R2B8 grid, where vn's FP32 storage alone drives
+    w's error above it (5e-3 stated)."""
+    return 5e-3 if (field == "w" and workload.startswith("r2b8")) else 1e-4
+
+
 def step_algorithmic_bytes(C, E, K, nsub, r):
     """Compulsory HBM traffic of a whole step with perfect fusion, as the
     scope table's measurement section counts it: each substep's predictor
@@ -302,6 +309,7 @@ def bench_r2b5(args, D, torch, dev):
     G.close()
     res["mixed_rel_l2_vs_fp64"] = {k: float(np.linalg.norm(outs["mixed"][k] - outs["fp64"][k])
                                          / np.linalg.norm(outs["fp64"][k])) for k in FIELDS}
+    res["mixed_within_1e-4"] = all(v <= 1e-4 for v in res["mixed_rel_l2_vs_fp64"].values())
     res["after_steps"] = spec["steps"]
     res["diag"] = diags
     return res
@@ -723,6 +731,8 @@ def main():
                          "step_hbm_effective_frac": round(b_mix / (ms2 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          "speedup_vs_fp64": ms / ms2, "rel_l2_vs_fp64": errs,
                          "after_steps": 2 * args.steps + args.warmup,
+                         "stated_bound": {k: mixed_bound(args.workload, k) for k in FIELDS},
+                         "within_stated_bound": all(errs[k] <= mixed_bound(args.workload, k) for k in FIELDS),
                          "mass_rel_diff_vs_fp64": d2["mass"] / diag["mass"] - 1.0,
                          "tiles": {k: f"{t}x{l}" for k, (t, l) in R2["tiles"].items()},
                          "kernels": {n: round(1e3 * t / c, 2) for n, (c, t) in R2["prof"].items() if c}}

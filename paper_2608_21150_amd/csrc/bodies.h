@@ -1198,9 +1198,10 @@ struct BCol {
 // Vertex quantities of the diffusion's first pass: the least-squares vertex
 // vector (x, y, z) and the relative vorticity.  FP32 keeps them interleaved
 // per vertex, one 16-byte record that one load brings in (diff_edge1 -46 %
-// on R2B8); FP64 keeps four planes [4][K][vs] (x, y, z, vorticity), since
-// its 32-byte records need two half-record accesses per vertex and measured
-// slower than the planes.  Index i = level * vs + vertex; plane = K * vs.
+// on R2B8); FP64 keeps two planes of 16-byte pairs, (x, y) then (z,
+// vorticity), each [K][vs]: two loads per vertex (diff_edge1 -10 % against
+// four planes), where 32-byte records were slower than four planes.  Index
+// i = level * vs + vertex; plane = K * vs values.
 template <typename R>
 struct alignas(4 * sizeof(R)) VVec {
   R x, y, z, zeta;
@@ -1212,17 +1213,19 @@ struct VertexQ {
     if constexpr (kInterleaved) {
       return reinterpret_cast<const VVec<R>*>(base)[i];
     } else {
-      return VVec<R>{base[i], base[plane + i], base[2 * plane + i], base[3 * plane + i]};
+      using R2 = R __attribute__((ext_vector_type(2)));
+      const R2 a = reinterpret_cast<const R2*>(base)[i];
+      const R2 b = reinterpret_cast<const R2*>(base + 2 * plane)[i];
+      return VVec<R>{a.x, a.y, b.x, b.y};
     }
   }
   __device__ __forceinline__ static void store(R* __restrict__ base, size_t plane, size_t i, const VVec<R>& v) {
     if constexpr (kInterleaved) {
       reinterpret_cast<VVec<R>*>(base)[i] = v;
     } else {
-      base[i] = v.x;
-      base[plane + i] = v.y;
-      base[2 * plane + i] = v.z;
-      base[3 * plane + i] = v.zeta;
+      using R2 = R __attribute__((ext_vector_type(2)));
+      reinterpret_cast<R2*>(base)[i] = R2{v.x, v.y};
+      reinterpret_cast<R2*>(base + 2 * plane)[i] = R2{v.z, v.zeta};
     }
   }
 };
