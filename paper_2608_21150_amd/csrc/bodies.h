@@ -278,7 +278,7 @@ struct BEdge {
     int kb;
   };
   static constexpr bool kXcdRanges = false;  // round-robin tile order (see the top of this file)
-  static constexpr int kThreads = 256;
+  static constexpr int kThreads = EdgeTiles::kTileE;
   // LDS of the fused form: per level parity, vn of the staged edges, vt and
   // K_e of the tile and its rhombus edges, vorticity at the tile's vertices
   static constexpr int kBuf = EdgeTiles::XM + 2 * EdgeTiles::XV + EdgeTiles::VM;
@@ -380,7 +380,7 @@ struct BEdge {
       gather(g, args, bx, by);
   }
 
-  // Fused form: the block's tile of 256 edges stages, at every level, vn of
+  // Fused form: the block's tile of kTileE edges stages, at every level, vn of
   // the tile, of its rhombus edges, of their rhombus edges and of the edges
   // around the tile's vertices in LDS (host tables list them), forms vt and
   // K_e on the tile and its rhombus edges and the vorticity at the tile's

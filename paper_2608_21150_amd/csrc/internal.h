@@ -72,11 +72,14 @@ enum VertTab {
 // staged sets of one tile must fit the fixed capacities below; grids whose
 // numbering scatters neighbours further (et_ok = 0) keep separate
 // vorticity/kinetic-energy and edge passes.
+// Tiles of 512 edges: against 256, the staged halo is a smaller share of a
+// tile (R2B8 FP64 edge_pred 10.1 -> 9.4 ms, edge_corr 8.5 -> 7.9 ms; mixed
+// unchanged overall); the FP64 buffers fill the 64 KB of LDS of a block.
 struct EdgeTiles {
-  static constexpr int kTileE = 256;  // edges per tile (= threads per block)
-  static constexpr int XM = 768;      // staged edges per tile
-  static constexpr int XV = 512;      // edges with vt and K_e per tile
-  static constexpr int VM = 256;      // vertices per tile
+  static constexpr int kTileE = 512;  // edges per tile (= threads per block)
+  static constexpr int XM = 1536;     // staged edges per tile
+  static constexpr int XV = 1024;     // edges with vt and K_e per tile
+  static constexpr int VM = 512;      // vertices per tile
 };
 
 int build_host_grid(const dc_grid_desc* desc, HostGrid* g, std::string* err);
