@@ -763,8 +763,20 @@ struct BCol {
           // just read by the other lanes, so mostly from cache), which measured
           // faster there
           double dm = 0.0, dth = 0.0;
+          // this level's edge and own loads first: the wave barriers of the
+          // LDS exchange below keep later loads from moving above them
+          const R* vr = pvn + (size_t)j * g.es;
+          R vq[3], gq[3] = {R(0), R(0), R(0)};
+          R tw0v = R(0);
+    #pragma unroll
+          for (int q = 0; q < 3; ++q) vq[q] = vr[ie[q]];
+          if (i >= 1) {
+            const R* gr = pgw + (size_t)j * g.es;
+    #pragma unroll
+            for (int q = 0; q < 3; ++q) gq[q] = gr[ie[q]];
+            tw0v = ptw0[(size_t)j * cs + c];
+          }
           {
-            const R* vr = pvn + (size_t)j * g.es;
             const double* rr = prho + (size_t)j * cs;
             const double* tr = pth + (size_t)j * cs;
             if (CORR) {
@@ -772,14 +784,12 @@ struct BCol {
               s_stg[p][1][cl] = cur.th;
               __builtin_amdgcn_wave_barrier();
             }
-            R vq[3];
             if (cf.miura) {
               // Miura edge values stored by the upwind pass
               const double* er = prhoe + (size_t)j * g.es;
               const double* et = pthe + (size_t)j * g.es;
     #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                vq[q] = vr[ie[q]];
                 const double fm = er[ie[q]] * (double)vq[q];
                 dm += kd[q] * fm;
                 dth += kd[q] * (fm * et[ie[q]]);
@@ -787,7 +797,6 @@ struct BCol {
             } else {
       #pragma unroll
               for (int q = 0; q < 3; ++q) {
-                vq[q] = vr[ie[q]];
                 double rn, tn;
                 if (CORR) {
                   // the LDS read is unconditional (masked index), the memory
@@ -831,7 +840,7 @@ struct BCol {
             // row of half level j, then one step of the down sweep
             double tw;
             if (CORR) {
-              tw = cf.a0 * (double)ptw0[(size_t)j * cs + c] + cf.a1 * col_tw<R>(pgw, vert, K1, g.es, ws_up, cur.ws, nx.ws, j, ie, inv_area);
+              tw = cf.a0 * (double)tw0v + cf.a1 * col_tw_g<R>(gq, vert, K1, ws_up, cur.ws, nx.ws, j, inv_area);
             } else {
               tw = col_tw<R>(pgw, vert, K1, g.es, w_up, cur.w, nx.w, j, ie, inv_area);
               ptw0[(size_t)j * cs + c0] = (R)tw;
