@@ -744,6 +744,10 @@ struct BCol {
     // exner stay in registers for the increment updates after the solve
     // instead of being read again (16-row chunks would spill heavily)
     constexpr bool kKeep = CORR && LM <= 12;
+    // 12-row chunks keep rho and theta_v but read exner again: keeping all
+    // three spilled (R2B8 column_corr -1 % FP64, -4 % mixed without them);
+    // 8-row chunks keep all three (reading exner again: +4 %)
+    constexpr bool kKeepEx = kKeep && LM <= 8;
     double sv_r[LM + 2], sv_t[LM + 2], sv_e[LM + 2];
     const double ric0 = cur.ric, atil0 = cur.atil;
     sv_r[0] = cur.rho;
@@ -1140,7 +1144,7 @@ struct BCol {
       if (kKeep) {
         lv.rho = sv_r[0];
         lv.th = sv_t[0];
-        lv.ex = sv_e[0];
+        lv.ex = kKeepEx ? sv_e[0] : pex[(size_t)h * cs + c];
         lv.thp = lv.th - vert[VT_THREF * K1 + h];
         lv.exp_ = lv.ex - vert[VT_EXREF * K1 + h];
         lv.ric = ric0;
@@ -1173,7 +1177,7 @@ struct BCol {
           if (kKeep) {
             nx.rho = sv_r[i + 1];
             nx.th = sv_t[i + 1];
-            nx.ex = sv_e[i + 1];
+            nx.ex = kKeepEx ? sv_e[i + 1] : pex[(size_t)jn * cs + c];
             nx.thp = nx.th - vert[VT_THREF * K1 + jn];
             nx.exp_ = nx.ex - vert[VT_EXREF * K1 + jn];
           } else {
