@@ -5,7 +5,12 @@ at any size.  Two steps of dt 30 s with 5 substeps from the jet state, in the
 mixed form (the benchmark's) and in FP64: total mass conserved to round-off,
 no non-finite value, theta-mass conserved to round-off, and mixed within
 1e-4 relative L2 of FP64 on vn, rho, exner and theta_v (the bound asserted
-on R2B5 after 10 steps); w, still tiny after 60 s, within its stated 5e-3."""
+on R2B5 after 10 steps); w, still tiny after 60 s, within its stated 5e-3.
+The step's parts at the same size: the area-weighted sum of the
+predictor's div vn* vanishes on the closed sphere at every level (each
+edge's flux leaves one cell and enters the other), w* keeps its boundary
+rows at zero, and predictor then corrector equals one substep (equal
+fixed-order diagnostics)."""
 import numpy as np
 import pytest
 
@@ -52,3 +57,39 @@ def test_r2b8_full_size_invariants():
     # of vn alone sets an absolute floor on its error (the divergence of vn's
     # rounding): its relative error is stated separately (2.5e-3 measured)
     assert errs["w"] <= 5e-3, errs["w"]
+
+
+@pytest.mark.timeout(600)
+def test_r2b8_full_size_parts():
+    spec = WORKLOADS["r2b8_k90"]
+    g0 = make_grid(spec["n"], spec["k"])
+    S, vert = initial_state(g0, spec["n_lev"], spec["z_top"], **spec["state"])
+    K = spec["n_lev"]
+    dtau = spec["dt"] / spec["nsub"]
+    G = D.Grid(g0, vert, sfc=True)
+    a = D.State(G, diffusion="none")
+    a.write(S)
+    m0 = a.diag()["mass"]
+    a.part("predictor", dtau, 1)
+    div = a.read_work("div")
+    area = np.asarray(g0["cell_area"], dtype=np.float64)
+    net = np.abs(div @ area)
+    scale = np.abs(div) @ area
+    print("R2B8 sum A div vn* / sum A |div vn*|: max over levels", float(np.max(net / scale)))
+    assert np.all(net <= 1e-12 * scale), float(np.max(net / scale))
+    del div
+    wp = a.read_work("w_pred")
+    assert np.all(np.isfinite(wp))
+    assert not np.any(wp[0]) and not np.any(wp[K])
+    del wp
+    assert a.diag()["mass"] == m0  # the predictor leaves the state alone
+    a.part("corrector", dtau, 1)
+    b = D.State(G, diffusion="none")
+    b.write(S)
+    b.step(dtau, 1)
+    da, db = a.diag(), b.diag()
+    for k in ("mass", "theta_mass", "max_abs_w", "max_abs_vn"):
+        assert da[k] == db[k], (k, da[k], db[k])
+    a.close()
+    b.close()
+    G.close()
