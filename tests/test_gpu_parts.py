@@ -1,7 +1,8 @@
 """The step in parts against the oracle's parts, through the C ABI: the
 first level of the paper's verification hierarchy (Section 4.4), which
 checks each segment between halo exchanges on the same input fields with a
-relative-error tolerance of 1e-12.
+relative-error tolerance of 1e-12; and its second level, whole steps run
+beside the reference on copies of the reference's fields at every step.
 
 Segments: the predictor (advective tendencies at the substep start, the
 momentum update to vn*, the implicit solve for w*, with its intermediates
@@ -227,4 +228,34 @@ def test_part_errors():
     none = D.State(G, diffusion="none")
     assert D.lib.dc_dycore_part(none.handle, 2, 60.0, 1) == D.DC_ESTATE
     none.close()
+    G.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL), ("mixed", 1e-5)])
+def test_second_level_step_by_step(precision, tol):
+    """The paper's second verification level (Section 4.4): the GPU step runs
+    beside the reference on copies of the reference's fields, so that each
+    step is checked on its own and errors do not accumulate.  Five whole
+    steps (substeps and diffusion) of config 1 from the seeded state: at
+    every step the GPU state is overwritten with the oracle's, both advance
+    one step, and every field agrees within the tolerance."""
+    g0, S, vert, spec = case()
+    dt, nsub = spec["dt"], spec["nsub"]
+    og = OGrid(g0, vert)
+    p = default_params()
+    wts = O.vertex_lsq_weights(og)
+    G = D.Grid(g0, vert)
+    st = D.State(G, precision=precision)
+    worst = {k: 0.0 for k in FIELDS}
+    for _ in range(5):
+        st.write(S)
+        st.step(dt, nsub)
+        got = st.read()
+        S = O.step(og, S, dt, nsub, p, wts=wts)
+        for k in FIELDS:
+            worst[k] = max(worst[k], rel_l2(got[k], S[k]))
+    print(precision, "worst per-step rel L2:", worst)
+    for k in FIELDS:
+        assert worst[k] <= tol, (precision, k, worst[k])
+    st.close()
     G.close()
