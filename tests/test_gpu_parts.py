@@ -259,3 +259,24 @@ def test_second_level_step_by_step(precision, tol):
         assert worst[k] <= tol, (precision, k, worst[k])
     st.close()
     G.close()
+
+
+@pytest.mark.parametrize("dtau", [600.0, 3000.0])
+def test_predictor_part_large_courant(dtau):
+    """The column solve at large vertical Courant numbers (sound crosses
+    many layers per substep: c dtau / dz up to ~1000 on config 1's 1 km
+    layers): w* from the partition-method solve matches the oracle's Thomas
+    solve, itself pinned against dense LU, at 1e-12."""
+    g0, S, vert, spec = case()
+    og = OGrid(g0, vert)
+    ref = oracle_predictor(og, default_params(), S, dtau)
+    G = D.Grid(g0, vert)
+    st = D.State(G)
+    st.write(S)
+    st.part("predictor", dtau, 1)
+    for n in ("w_pred", "vn_pred", "t_w"):
+        err = rel_l2(st.read_work(n), ref[n])
+        print(dtau, n, err)
+        assert err <= TOL, (dtau, n, err)
+    st.close()
+    G.close()
