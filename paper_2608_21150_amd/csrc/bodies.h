@@ -622,6 +622,19 @@ struct LevIn {
   R tw0;
 };
 
+// 1 / x for the column solve's positive divisors (pivots >= 1, rho theta_v,
+// exner rho, 1 + dtau tau): the hardware's reciprocal estimate refined by two
+// Newton-Raphson steps, e <- 1 - x r, r <- r + r e (each step doubles the
+// correct bits), within about an ulp of the rounded quotient and shorter on
+// the solve's recurrence than a correctly rounded division.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // State of one level of a column: full level j and half level j.
 struct ColLev {
   double rho, th, ex, thp, exp_;  // full level j
@@ -849,7 +862,7 @@ struct BCol {
             // (level h of chunk p > 0 is also stored by chunk p - 1: the same value)
             if (!CORR) pdv[(size_t)j * cs + c0] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
           }
-          const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
+          const double b = dtau * cf.rd_cvd * cur.ex * rcp_nr(cur.rho * cur.th);
           const double beta = b * idzf[j];
           const double drx = -dtau * (dm + oneme * (cur.ric * cur.w - nx.ric * nx.w) * idzf[j]);
           const double dxx = -b * (dth + oneme * (cur.atil * cur.w - nx.atil * nx.w) * idzf[j]);
@@ -873,12 +886,12 @@ struct BCol {
             // one reciprocal per row: the pivots are >= 1, so multiplying by
             // it loses nothing against three divisions
             if (i == 1) {
-              const double r = 1.0 / B;
+              const double r = rcp_nr(B);
               cpv[0] = C * r;
               dpv[0] = rhs * r;
               lpv[0] = A * r;
             } else {
-              const double r = 1.0 / (B - A * cpv[i - 2]);
+              const double r = rcp_nr(B - A * cpv[i - 2]);
               cpv[i - 1] = C * r;
               dpv[i - 1] = (rhs - A * dpv[i - 2]) * r;
               lpv[i - 1] = -A * lpv[i - 2] * r;
@@ -1010,7 +1023,7 @@ struct BCol {
             // (level h of chunk p > 0 is also stored by chunk p - 1: the same value)
             if (!CORR) pdv[(size_t)j * cs + c0] = (R)kd[0] * vq[0] + (R)kd[1] * vq[1] + (R)kd[2] * vq[2];
           }
-          const double b = dtau * cf.rd_cvd * cur.ex / (cur.rho * cur.th);
+          const double b = dtau * cf.rd_cvd * cur.ex * rcp_nr(cur.rho * cur.th);
           const double beta = b * idzf[j];
           const double drx = -dtau * (dm + oneme * (cur.ric * cur.w - nx.ric * nx.w) * idzf[j]);
           const double dxx = -b * (dth + oneme * (cur.atil * cur.w - nx.atil * nx.w) * idzf[j]);
@@ -1034,12 +1047,12 @@ struct BCol {
             // one reciprocal per row: the pivots are >= 1, so multiplying by
             // it loses nothing against three divisions
             if (i == 1) {
-              const double r = 1.0 / B;
+              const double r = rcp_nr(B);
               cpv[0] = C * r;
               dpv[0] = rhs * r;
               lpv[0] = A * r;
             } else {
-              const double r = 1.0 / (B - A * cpv[i - 2]);
+              const double r = rcp_nr(B - A * cpv[i - 2]);
               cpv[i - 1] = C * r;
               dpv[i - 1] = (rhs - A * dpv[i - 2]) * r;
               lpv[i - 1] = -A * lpv[i - 2] * r;
@@ -1124,13 +1137,13 @@ struct BCol {
     // (row i of the chunk is half level s + i; w*(h) of the chunk above is
     // needed only by chunk 0, where it is the w = 0 boundary)
     const int e = s + n;
-    const double w_below = (e < K) ? xb / (1.0 + dtau * tau[e]) : 0.0;
+    const double w_below = (e < K) ? xb * rcp_nr(1.0 + dtau * tau[e]) : 0.0;
     if (!CORR) {
   #pragma unroll
       for (int i = 0; i < LM; ++i) {
         if (i < n) {
           const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
-          pw_out[(size_t)(s + i) * cs + c0] = x / (1.0 + dtau * tau[s + i]);
+          pw_out[(size_t)(s + i) * cs + c0] = x * rcp_nr(1.0 + dtau * tau[s + i]);
         }
       }
     }
@@ -1168,7 +1181,7 @@ struct BCol {
           double w1 = w_below;
           if (i < n) {
             const double x = dpv[i] - cpv[i] * xb - lpv[i] * xa;
-            w1 = x / (1.0 + dtau * tau[s + i]);
+            w1 = x * rcp_nr(1.0 + dtau * tau[s + i]);
             pw_out[(size_t)(s + i) * cs + c0] = w1;
           }
           const bool bottom = j + 1 >= K;
@@ -1189,7 +1202,7 @@ struct BCol {
             nx.atil = 0.0;
           }
           if (i >= 1 || p == 0) {
-            const double b = dtau * cf.rd_cvd * lv.ex / (lv.rho * lv.th);
+            const double b = dtau * cf.rd_cvd * lv.ex * rcp_nr(lv.rho * lv.th);
             const double beta = b * idzf[j];
             const double drho = drxv[i] - dtau * eta * (lv.ric * w0 - nx.ric * w1) * idzf[j];
             const double dex = dxxv[i] - beta * (eta * lv.atil * w0 - eta * nx.atil * w1);
@@ -1198,7 +1211,7 @@ struct BCol {
               const size_t r = (size_t)j * cs + c0;
               prho_out[r] = rho_new;
               pex_out[r] = lv.ex + dex;
-              pth_out[r] = lv.th + lv.th * (lv.rho * cf.cvd_rd * dex - drho * lv.ex) / (lv.ex * rho_new);
+              pth_out[r] = lv.th + lv.th * (lv.rho * cf.cvd_rd * dex - drho * lv.ex) * rcp_nr(lv.ex * rho_new);
             }
           }
           w0 = w1;
