@@ -263,8 +263,9 @@ dc_status dc_dycore_part(dc_state *st, int32_t part, double dt, int32_t nsubstep
  *                    1..K-1 (rows 0 and K are returned as 0)         [K+1][C]
  *   DC_WORK_DIV      div vn* (input of the corrector's damping)      [K][C]
  * Mixed precision: vn*, Y, T_w and div vn* are stored in FP32.  n must equal
- * the element count.  DC_ESTATE if no DC_PART_PREDICTOR ran since the state
- * was created or last stepped. */
+ * the element count.  DC_ESTATE if no DC_PART_PREDICTOR ran since the
+ * state was created or its workspace was last overwritten (by a step, a
+ * diffusion part, tuning, an ensemble step or a surrogate collection). */
 enum { DC_WORK_VN_PRED = 0, DC_WORK_Y, DC_WORK_W_PRED, DC_WORK_T_W, DC_WORK_DIV, DC_WORK_COUNT };
 dc_status dc_state_read_work(dc_state *st, int32_t which, double *host, size_t n);
 /* Synchronising conservation diagnostics of the current buffer (fixed
